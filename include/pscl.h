@@ -1,0 +1,156 @@
+/*
+ * pscl - CRC-aided list decoding of polar codes on AMD Instinct MI355X
+ * (gfx950), after "Fast List Decoders for Polar Codes" (Sarkis, Giard, Vardy,
+ * Thibeault, Gross).
+ *
+ * The decoder runs list decoding on the decoding tree of the code (Sec. II-D,
+ * Sec. III): min-sum F (eq. (f)), G (eq. (g)) and Combine (eq. (combine)) on
+ * every internal node of every active path; Rate-0, Rate-1 (Chase-II over two
+ * least reliable bits), repetition and SPC (Chase-II over four least reliable
+ * bits) list decoders at the leaves, each scoring its candidates with the
+ * codeword metric of eq. (pm); candidate selection keeping the L best paths
+ * (Alg. 1); and the final choice of the most reliable path that satisfies the
+ * CRC (Sec. II-B).
+ *
+ * Conventions (all entry points):
+ *  - frozen_mask: host array of N bytes, 1 = frozen (fixed to 0), 0 = carries
+ *    a bit.  K = number of zero bytes.
+ *  - The K unfrozen positions, in increasing position order, carry the K - r
+ *    payload bits followed by the r CRC bits ("CRC inside K").
+ *  - CRC: generator x^r + crc_poly (crc_poly in normal form, without the x^r
+ *    term), register initialised to 0, bits fed most significant first, no
+ *    reflection, no final XOR.  r = crc_len in [0, 64]; 0 = no CRC.
+ *  - LLRs: positive favours bit 0 (Sec. II-A, eq. (sc:h)).  F x N row-major
+ *    device array of float (PSCL_F32), int16 in [-32767, 32767] (PSCL_I16) or
+ *    int8 in [-127, 127] (PSCL_I8).  Integer G results saturate to that range.
+ *  - Ties: equal candidate metrics are ordered by enumeration index (source
+ *    path slot, then candidate rank); the final pick prefers the lower slot.
+ *
+ * Ownership: the caller owns every device buffer passed in; a plan owns its
+ * device schedule, tables and workspace.  Decoding is asynchronous on the
+ * caller's HIP stream and never allocates.  All device pointers must be
+ * accessible from the device that was current when the plan was created.
+ *
+ * Errors: every function returns a status code and never throws.  A HIP
+ * failure reported by the runtime (including asynchronous faults of earlier
+ * work) is returned as PSCL_E_HIP.  "No path satisfies the CRC" is not an
+ * error: crc_ok = 0 and the most reliable path is returned.
+ */
+#ifndef PSCL_H
+#define PSCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSCL_OK = 0,
+    PSCL_E_INVALID = 1,     /* invalid argument */
+    PSCL_E_UNSUPPORTED = 2, /* valid, but no kernel for this combination */
+    PSCL_E_NOMEM = 3,       /* device allocation failed */
+    PSCL_E_HIP = 4,         /* HIP runtime error */
+    PSCL_E_NODEV = 5        /* no usable gfx950 device */
+} pscl_status;
+
+typedef enum { PSCL_F32 = 0, PSCL_I16 = 1, PSCL_I8 = 2 } pscl_dtype;
+
+/* Decoding-tree modes (Table 1): PSCL_MODE_TREE uses the Rate-0, Rate-1,
+ * repetition and SPC list decoders ("unrolled Dec-SPC-4" with spc_max = 4);
+ * PSCL_MODE_SCL_LEAVES splits every node down to single bits ("unrolled
+ * SC-list"). */
+typedef enum { PSCL_MODE_TREE = 0, PSCL_MODE_SCL_LEAVES = 1 } pscl_mode;
+
+/* Schedule operations, as reported by pscl_schedule. */
+typedef enum {
+    PSCL_OP_F = 0,    /* alpha_l = F(alpha_v), eq. (f) */
+    PSCL_OP_G = 1,    /* alpha_r = G(alpha_v, beta_l), eq. (g) */
+    PSCL_OP_COMB = 2, /* beta_v = Combine(beta_l, beta_r), eq. (combine) */
+    PSCL_OP_R0 = 3,   /* Rate-0 list decoder, Sec. III-B */
+    PSCL_OP_REP = 4,  /* repetition list decoder, Sec. III-E */
+    PSCL_OP_R1 = 5,   /* Rate-1 list decoder, Sec. III-C */
+    PSCL_OP_SPC = 6   /* SPC list decoder, Sec. III-D */
+} pscl_op_type;
+
+typedef struct pscl_plan pscl_plan;
+
+/* Human-readable name of a status code (static string). */
+const char* pscl_status_str(pscl_status s);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int pscl_version(void);
+
+/*
+ * Host-only schedule compiler (Sec. II-D: tree optimisation; Listing 2: the
+ * unrolled operation sequence).  Classifies every node of the decoding tree
+ * of (N, frozen_mask) and emits the operations in decoding order.  Needs no
+ * GPU.
+ *   ops: host array of capacity cap entries, 4 int32 each:
+ *        {pscl_op_type, log2(node size), side (0 = left child, 1 = right child
+ *        or root), active paths after the operation}.
+ *   *n_ops: number of operations (written even when cap is too small, in
+ *   which case PSCL_E_INVALID is returned).
+ * spc_max: largest SPC node (4 = Dec-SPC-4; up to N allowed; values below 4
+ * disable SPC nodes).  L: list size in {1, 2, 4, 8, 16, 32}.
+ */
+pscl_status pscl_schedule(int N, const uint8_t* frozen_mask, int L, int spc_max,
+                          int mode, int32_t* ops, int cap, int* n_ops);
+
+/*
+ * Create a decoding plan on the current HIP device.
+ *   N: power of two in [2, 4096].  K: number of unfrozen positions (1..N).
+ *   crc_poly, crc_len: see the conventions above (crc_len <= K).
+ *   L: list size in {1, 2, 4, 8, 16, 32}.  dtype: pscl_dtype.
+ *   spc_max, mode: see pscl_schedule.
+ * Allocates the device schedule, CRC tables and decoding workspace.
+ * Returns PSCL_E_INVALID on bad arguments, PSCL_E_NODEV without a gfx950
+ * device, PSCL_E_NOMEM / PSCL_E_HIP on runtime failures.  *out is set only on
+ * success.
+ */
+pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                             int crc_len, int L, int dtype, int spc_max, int mode,
+                             pscl_plan** out);
+
+/* Release a plan (NULL allowed).  Synchronises the device first. */
+void pscl_plan_destroy(pscl_plan* plan);
+
+/*
+ * Decode F frames (Sec. III; Alg. 1; final CRC choice, Sec. II-B).
+ *   llr: device, F x N row-major in the plan's dtype.
+ *   u_hat: device, F x K bytes (0/1): the decided bits at the unfrozen
+ *          positions in increasing position order (payload then CRC).
+ *   crc_ok: device, F bytes or NULL: 1 if the chosen path satisfies the CRC
+ *          (always 1 when crc_len = 0).
+ *   pm: device, F entries or NULL: path metric of the chosen path, float for
+ *       PSCL_F32, int32 for the integer dtypes.
+ *   stream: hipStream_t or NULL for the default stream.
+ * F = 0 is a no-op.  Returns PSCL_E_INVALID on null required pointers or
+ * F < 0.
+ */
+pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8_t* u_hat,
+                        uint8_t* crc_ok, void* pm, void* stream);
+
+/*
+ * One-call form decode(N, K, frozen_mask, crc_poly, L, llr) -> u_hat: builds
+ * (or reuses from a per-process cache keyed by every argument that shapes the
+ * plan) the plan for the Dec-SPC-4 tree and decodes.  Same buffers and
+ * errors as pscl_plan_create + pscl_decode.
+ */
+pscl_status pscl_decode_oneshot(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                                int crc_len, int L, int dtype, const void* llr, int64_t F,
+                                uint8_t* u_hat, uint8_t* crc_ok, void* stream);
+
+/* Launch shape chosen for a plan: frames per workgroup, threads per
+ * workgroup, workgroups, LDS bytes per workgroup, bytes of global workspace,
+ * first tree level whose LLR stage lives in global memory (n = none). */
+pscl_status pscl_plan_info(const pscl_plan* plan, int* frames_per_wg, int* threads,
+                           int* workgroups, int* lds_bytes, int64_t* workspace_bytes,
+                           int* first_global_stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

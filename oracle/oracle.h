@@ -62,8 +62,9 @@ int orc_crc(const uint8_t* bits, int nbits, uint64_t poly, int r, uint64_t* rem)
 int orc_polar_transform(uint8_t* v, int N);
 
 /* Select the L best of n candidates (Alg. 1): best = larger metric, ties go to
- * the smaller enumeration index; survivors are written to keep[] in increasing
- * enumeration index.  Returns the number kept (min(n, L)). */
+ * the smaller enumeration index.  keep[] receives the survivors' enumeration
+ * indices in slot order: best first when candidates were dropped (n > L),
+ * enumeration order when all are kept.  Returns the number kept (min(n, L)). */
 int orc_select(const double* pm, int n, int L, int* keep);
 
 /*

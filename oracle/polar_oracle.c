@@ -68,7 +68,9 @@ int orc_polar_transform(uint8_t* v, int N) {
 /* ------------------------------------------------------------------------ */
 /* Candidate selection (Alg. 1): keep the L candidates with the largest      */
 /* path metric; equal metrics are ordered by enumeration index (smaller      */
-/* first).  Survivors keep their enumeration order.                          */
+/* first).  The paper's heap leaves the order of the kept paths open; here,  */
+/* when candidates are dropped the survivors take slots best first, and when */
+/* all are kept they stay in enumeration order.                              */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -101,14 +103,9 @@ static int select_best(const double* pm, int n, int L, int* keep, double* gap, d
     qsort(k, (size_t)n, sizeof(cand_key), cand_cmp);
     *gap = k[L - 1].pm - k[L].pm;
     *at = fmax(fabs(k[L - 1].pm), fabs(k[L].pm));
-    uint8_t* mark = (uint8_t*)calloc((size_t)n, 1);
-    for (int i = 0; i < L; i++) mark[k[i].idx] = 1;
-    int m = 0;
-    for (int i = 0; i < n; i++)
-        if (mark[i]) keep[m++] = i;
-    free(mark);
+    for (int i = 0; i < L; i++) keep[i] = k[i].idx;
     free(k);
-    return m;
+    return L;
 }
 
 int orc_select(const double* pm, int n, int L, int* keep) {
