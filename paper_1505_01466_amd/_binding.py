@@ -1,0 +1,182 @@
+"""ctypes binding of libpscl.so.  Argument marshalling only: every step of
+decoding runs in the library's HIP kernels.  torch provides device memory
+and the current stream.
+
+The library must have been built (``python -m paper_1505_01466_amd.build`` or
+``__graft_entry__.build()``); importing this module fails loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpscl.so")
+
+PSCL_F32, PSCL_I16, PSCL_I8 = 0, 1, 2
+DTYPES = {"f32": PSCL_F32, "i16": PSCL_I16, "i8": PSCL_I8}
+MODE_TREE, MODE_SCL_LEAVES = 0, 1
+OP_NAMES = ("F", "G", "COMB", "R0", "REP", "R1", "SPC")
+
+_STATUS = {
+    0: "ok",
+    1: "invalid argument",
+    2: "unsupported configuration",
+    3: "device out of memory",
+    4: "HIP runtime error",
+    5: "no gfx950 device",
+}
+
+
+class PsclError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_STATUS.get(status, 'unknown')} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libpscl.so not found at {LIB_PATH}; build it with "
+            "`python -m paper_1505_01466_amd.build` (hipcc, gfx950)"
+        )
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_i64, c_u64, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    ip = ctypes.POINTER(c_int)
+    lib.pscl_status_str.argtypes = [c_int]
+    lib.pscl_status_str.restype = ctypes.c_char_p
+    lib.pscl_version.argtypes = []
+    lib.pscl_version.restype = c_int
+    lib.pscl_schedule.argtypes = [c_int, u8p, c_int, c_int, c_int, i32p, c_int, ip]
+    lib.pscl_schedule.restype = c_int
+    lib.pscl_plan_create.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, c_int, c_int,
+                                     ctypes.POINTER(vp)]
+    lib.pscl_plan_create.restype = c_int
+    lib.pscl_plan_destroy.argtypes = [vp]
+    lib.pscl_plan_destroy.restype = None
+    lib.pscl_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp]
+    lib.pscl_decode.restype = c_int
+    lib.pscl_decode_oneshot.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, vp, c_i64,
+                                        vp, vp, vp]
+    lib.pscl_decode_oneshot.restype = c_int
+    lib.pscl_plan_info.argtypes = [vp, ip, ip, ip, ip, ctypes.POINTER(c_i64), ip]
+    lib.pscl_plan_info.restype = c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise PsclError(status, what)
+
+
+def _mask(frozen) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(frozen, dtype=np.uint8))
+
+
+def _u8p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def schedule(N: int, frozen, L: int, spc_max: int = 4, mode: int = MODE_TREE) -> np.ndarray:
+    """Operation schedule of the decoding tree (host only, no GPU needed):
+    rows of (op type, log2 node size, side, active paths after)."""
+    fz = _mask(frozen)
+    n = ctypes.c_int(0)
+    cap = 4 * N + 8
+    ops = np.zeros((cap, 4), dtype=np.int32)
+    _check(lib.pscl_schedule(N, _u8p(fz), L, spc_max, mode,
+                             ops.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap,
+                             ctypes.byref(n)), "pscl_schedule")
+    return ops[: n.value].copy()
+
+
+def _stream_handle(device):
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A decoding plan on the current device (see pscl_plan_create)."""
+
+    def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int,
+                 dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE):
+        import torch
+
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        self.N, self.K, self.L, self.dtype = N, K, L, dtype
+        self.crc_poly, self.crc_len, self.spc_max, self.mode = crc_poly, crc_len, spc_max, mode
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        fz = _mask(frozen)
+        h = ctypes.c_void_p(None)
+        _check(lib.pscl_plan_create(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype], spc_max,
+                                    mode, ctypes.byref(h)), "pscl_plan_create")
+        self._h = h
+
+    def info(self) -> dict:
+        fw, nt, wg, lds, glob = (ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(),
+                                 ctypes.c_int())
+        ws = ctypes.c_int64()
+        _check(lib.pscl_plan_info(self._h, ctypes.byref(fw), ctypes.byref(nt), ctypes.byref(wg),
+                                  ctypes.byref(lds), ctypes.byref(ws), ctypes.byref(glob)),
+               "pscl_plan_info")
+        return {"frames_per_wg": fw.value, "threads": nt.value, "workgroups": wg.value,
+                "lds_bytes": lds.value, "workspace_bytes": ws.value,
+                "first_global_stage": glob.value}
+
+    def decode(self, llr, u_hat=None, crc_ok=None, pm=None):
+        """Decode llr (F x N device tensor in the plan's dtype) into
+        (u_hat F x K uint8, crc_ok F uint8, pm F float32/int32)."""
+        import torch
+
+        want = {"f32": torch.float32, "i16": torch.int16, "i8": torch.int8}[self.dtype]
+        if llr.dtype != want or llr.dim() != 2 or llr.shape[1] != self.N:
+            raise ValueError(f"llr must be an F x {self.N} {want} tensor")
+        if llr.device != self.device or not llr.is_contiguous():
+            raise ValueError("llr must be a contiguous tensor on the plan's device")
+        F = llr.shape[0]
+        if u_hat is None:
+            u_hat = torch.empty((F, self.K), dtype=torch.uint8, device=self.device)
+        if crc_ok is None:
+            crc_ok = torch.empty(F, dtype=torch.uint8, device=self.device)
+        if pm is None:
+            pm = torch.empty(F, dtype=torch.float32 if self.dtype == "f32" else torch.int32,
+                             device=self.device)
+        _check(lib.pscl_decode(self._h, llr.data_ptr(), F, u_hat.data_ptr(), crc_ok.data_ptr(),
+                               pm.data_ptr(), _stream_handle(self.device)), "pscl_decode")
+        return u_hat, crc_ok, pm
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pscl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr, dtype: str = "f32"):
+    """decode(N, K, frozen_mask, crc_poly, L, llr[F x N]) -> (u_hat[F x K], crc_ok[F]) with the
+    plan cached inside the library (Dec-SPC-4 tree)."""
+    import torch
+
+    F = llr.shape[0]
+    u_hat = torch.empty((F, K), dtype=torch.uint8, device=llr.device)
+    crc_ok = torch.empty(F, dtype=torch.uint8, device=llr.device)
+    fz = _mask(frozen)
+    _check(lib.pscl_decode_oneshot(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype],
+                                   llr.data_ptr(), F, u_hat.data_ptr(), crc_ok.data_ptr(),
+                                   _stream_handle(llr.device)), "pscl_decode_oneshot")
+    return u_hat, crc_ok

@@ -1,0 +1,142 @@
+"""The C-ABI library: it loads, exports every declared entry point, and its
+host-only schedule compiler builds the decoding tree of Sec. II-D.  No GPU
+needed (no decode calls)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1505_01466_amd as pk
+
+    return pk
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "pscl.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pscl_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(pk):
+    names = _declared_functions()
+    assert "pscl_decode" in names and "pscl_plan_create" in names
+    for name in names:
+        assert hasattr(pk.lib, name), name
+
+
+def test_status_strings_and_version(pk):
+    for s in range(6):
+        assert pk.lib.pscl_status_str(s)
+    assert pk.lib.pscl_version() >= 100
+
+
+def _golden_ops():
+    for line in open(os.path.join(GOLDEN, "fig1_code_8_4.txt")):
+        if line.startswith("fast_ssc_ops"):
+            return line.split()[1:]
+        if line.startswith("frozen"):
+            frozen_pos = [int(v) for v in line.split()[1:]]
+    raise AssertionError
+
+
+def test_schedule_of_fig2_code(pk):
+    frozen = np.zeros(8, np.uint8)
+    frozen[[0, 1, 2, 4]] = 1
+    ops = pk.schedule(8, frozen, L=4)
+    got = [f"{pk.OP_NAMES[t]}{1 << k}" for t, k, _, _ in ops]
+    assert got == _golden_ops()
+    # Rep<4> forks into 2 paths, SPC<4> into 2 x 8 -> capped at L = 4
+    assert [p for *_, p in ops] == [1, 2, 2, 4, 4]
+
+
+def _leaves(frozen, spc_max, mode):
+    out = []
+
+    def rec(f):
+        nv = len(f)
+        nf = int(f.sum())
+        if nv == 1:
+            out.append(("R0" if nf else "R1", 0))
+            return
+        if mode == 0:
+            if nf == nv:
+                return out.append(("R0", nv.bit_length() - 1))
+            if nf == 0:
+                return out.append(("R1", nv.bit_length() - 1))
+            if nf == nv - 1 and not f[-1]:
+                return out.append(("REP", nv.bit_length() - 1))
+            if nf == 1 and f[0] and 4 <= nv <= spc_max:
+                return out.append(("SPC", nv.bit_length() - 1))
+        rec(f[: nv // 2])
+        rec(f[nv // 2:])
+
+    rec(frozen)
+    return out
+
+
+@pytest.mark.parametrize("N,K,r,d", [(1024, 512, 8, 2.5), (2048, 1723, 32, 4.0),
+                                     (1024, 860, 32, 4.0), (4096, 3441, 32, 4.0)])
+@pytest.mark.parametrize("mode,spc_max", [(0, 4), (0, 4096), (1, 4)])
+def test_schedule_leaves_and_paths(pk, N, K, r, d, mode, spc_max):
+    code = synth.make_code(N, K, r, synth.CRC32_POLY, d)
+    L = 32
+    ops = pk.schedule(N, code.frozen, L, spc_max, mode)
+    leaves = [(pk.OP_NAMES[t], k) for t, k, _, _ in ops if t >= 3]
+    assert leaves == _leaves(code.frozen, spc_max, mode)
+    # every internal node appears as F, G, Combine in that order
+    n_int = sum(1 for t, *_ in ops if t == 0)
+    assert n_int == sum(1 for t, *_ in ops if t == 1) == sum(1 for t, *_ in ops if t == 2)
+    # list size grows by the candidate count, capped at L
+    P = 1
+    cands = {"R0": 1, "REP": 2, "SPC": 8}
+    for t, k, side, paths in ops:
+        name = pk.OP_NAMES[t]
+        if name in cands or name == "R1":
+            c = cands.get(name, 2 if k == 0 else 4)
+            P = min(L, P * c)
+        assert paths == P
+    # the covered leaf sizes add up to N
+    assert sum(1 << k for _, k in leaves) == N
+
+
+def test_schedule_rejects_bad_arguments(pk):
+    frozen = np.zeros(8, np.uint8)
+    n = ctypes.c_int()
+    buf = np.zeros(64, np.int32)
+    p = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    u8 = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert pk.lib.pscl_schedule(12, u8, 4, 4, 0, p, 16, ctypes.byref(n)) == 1  # N not 2^n
+    assert pk.lib.pscl_schedule(8, u8, 3, 4, 0, p, 16, ctypes.byref(n)) == 1  # L not 2^k
+    assert pk.lib.pscl_schedule(8, u8, 4, 4, 7, p, 16, ctypes.byref(n)) == 1  # bad mode
+    assert pk.lib.pscl_schedule(8, u8, 4, 4, 0, p, 0, ctypes.byref(n)) == 1  # no room
+    assert n.value == 1  # count still reported (root is one Rate-1 node)
+
+
+def test_plan_create_validates_before_touching_the_device(pk):
+    frozen = np.zeros(8, np.uint8)
+    frozen[:4] = 1
+    h = ctypes.c_void_p()
+    u8 = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    # K does not match the mask
+    assert pk.lib.pscl_plan_create(8, 5, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(h)) == 1
+    # crc longer than K
+    assert pk.lib.pscl_plan_create(8, 4, u8, 0x7, 8, 4, 0, 4, 0, ctypes.byref(h)) == 1
+    # bad dtype, bad L
+    assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 4, 9, 4, 0, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 64, 0, 4, 0, ctypes.byref(h)) == 1
+    assert not h.value
+
+
+def test_decode_rejects_null_plan(pk):
+    assert pk.lib.pscl_decode(None, None, 0, None, None, None, None) == 1

@@ -1,0 +1,177 @@
+"""Parity of the HIP decoder with the CPU oracle, element by element, on
+seeded synthetic frames (BPSK-AWGN, random payloads, CRC inside K).
+
+Integer LLRs must match bit for bit (decisions, CRC flags, path metrics);
+float32 must match decisions and CRC flags with metrics within 1e-5
+relative, except on frames the oracle reports as metric near-ties."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+from parity import batch, compare, gpu_decode, oracle_decode
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_01466_amd  # noqa: F401  (fails loudly without the library)
+
+
+# ---------------------------------------------------------------------------
+# Small and degenerate codes: every node class at the root and below, every
+# list size, both tree modes, SPC-4 and longer SPC nodes.
+# ---------------------------------------------------------------------------
+
+def _random_code(rng, N):
+    K = int(rng.integers(1, N + 1))
+    frozen = np.ones(N, np.uint8)
+    frozen[rng.choice(N, K, replace=False)] = 0
+    r = int(rng.integers(0, min(K - 1, 8) + 1))  # at least one payload bit
+    poly = {0: 0, 1: 0x1, 2: 0x3, 3: 0x3, 4: 0x3, 5: 0x5, 6: 0x3, 7: 0x9, 8: 0x07}[r]
+    return synth.PolarCode(N=N, K=K, r=r, poly=poly, design_ebn0_db=0.0, frozen=frozen)
+
+
+@pytest.mark.parametrize("dtype", ["i8", "i16", "f32"])
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32, 64])
+def test_small_codes(dtype, N):
+    rng = np.random.default_rng(1000 + N)
+    for trial in range(6):
+        code = _random_code(rng, N)
+        for L in (1, 2, 4, 8, 16, 32):
+            for mode, spc_max in ((0, 4), (0, N), (1, 4)):
+                _say(f"N={N} K={code.K} r={code.r} L={L} mode={mode} spc={spc_max} {dtype}")
+                b = synth.make_batch(code, 37, 1.0, (N, trial, L), dtype)
+                g = gpu_decode(code, L, b.llr, dtype, spc_max, mode)
+                o = oracle_decode(code, L, b.llr, dtype, spc_max, mode)
+                compare(g, o, dtype, f"N={N} L={L} mode={mode}")
+
+
+# ---------------------------------------------------------------------------
+# The workloads: (1024,512) CRC-8 L=4; (2048,1723) CRC-32 L=32;
+# (1024,860) CRC-32 L in {2..32}.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_1024_512_crc8_L4_f32(mode):
+    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 2000, 2.5, (1, mode), "f32")
+    _say(f"(1024,512) L=4 f32 mode={mode}")
+    g = gpu_decode(code, 4, b.llr, "f32", mode=mode)
+    o = oracle_decode(code, 4, b.llr, "f32", mode=mode)
+    exact = compare(g, o, "f32", "(1024,512)")
+    assert exact >= 0.99 * b.F
+    if mode == 1:
+        import oracle
+
+        s = oracle.decode_scl(1024, 512, code.frozen, code.poly, 8, 4, b.llr, "f32")
+        compare(g, s, "f32", "(1024,512) vs bit-by-bit SCL")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+@pytest.mark.parametrize("ebn0", [3.5, 4.0, 4.5])
+def test_2048_1723_crc32_L32(dtype, ebn0):
+    code, b = batch(2048, 1723, 32, synth.CRC32_POLY, 4.0, 256, ebn0, (2, int(ebn0 * 4)), dtype)
+    _say(f"(2048,1723) L=32 {dtype} {ebn0} dB")
+    g = gpu_decode(code, 32, b.llr, dtype)
+    o = oracle_decode(code, 32, b.llr, dtype)
+    compare(g, o, dtype, f"(2048,1723) {dtype} {ebn0}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i16"])
+@pytest.mark.parametrize("L", [2, 4, 8, 16, 32])
+def test_1024_860_crc32_list_sizes(dtype, L):
+    code, b = batch(1024, 860, 32, synth.CRC32_POLY, 4.0, 300, 4.0, (3, L), dtype)
+    _say(f"(1024,860) L={L} {dtype}")
+    g = gpu_decode(code, L, b.llr, dtype)
+    o = oracle_decode(code, L, b.llr, dtype)
+    compare(g, o, dtype, f"(1024,860) L={L}")
+
+
+@pytest.mark.parametrize("N,K,r,L,dtype", [(4096, 3441, 32, 32, "i8"), (4096, 2048, 32, 8, "f32"),
+                                           (256, 86, 8, 32, "i8"), (512, 430, 32, 2, "i16")])
+def test_other_lengths(N, K, r, L, dtype):
+    poly = synth.CRC8_POLY if r == 8 else synth.CRC32_POLY
+    code, b = batch(N, K, r, poly, 2.5 if K <= N // 2 else 4.0, 64, 3.0, (4, N, L), dtype)
+    _say(f"({N},{K}) L={L} {dtype}")
+    g = gpu_decode(code, L, b.llr, dtype)
+    o = oracle_decode(code, L, b.llr, dtype)
+    compare(g, o, dtype, f"({N},{K}) L={L}")
+
+
+# ---------------------------------------------------------------------------
+# Edge cases
+# ---------------------------------------------------------------------------
+
+def test_ragged_and_tiny_batches():
+    import paper_1505_01466_amd as pk
+
+    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 131, 2.0, 5, "i8")
+    plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 4, "i8")
+    for F in (1, 2, 3, 7, 64, 131):
+        _say(f"ragged F={F}")
+        g = gpu_decode(code, 4, b.llr[:F], "i8", plan=plan)
+        o = oracle_decode(code, 4, b.llr[:F], "i8")
+        compare(g, o, "i8", f"F={F}")
+
+
+def test_empty_batch_is_a_noop():
+    import torch
+
+    import paper_1505_01466_amd as pk
+
+    code = synth.make_code(256, 128, 8, synth.CRC8_POLY, 2.5)
+    plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 4, "f32")
+    llr = torch.zeros((0, 256), dtype=torch.float32, device="cuda")
+    u, ok, pm = plan.decode(llr)
+    torch.cuda.synchronize()
+    assert u.shape == (0, 128)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i8"])
+def test_degenerate_inputs(dtype):
+    """All-zero LLRs (every decision a tie) and sign-flipped codewords (no
+    path passes the CRC: the most reliable path is returned, crc_ok = 0)."""
+    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 40, 3.0, 6, dtype)
+    zeros = np.zeros_like(b.llr)
+    flipped = (-b.llr.astype(np.int64)).astype(b.llr.dtype) if dtype != "f32" else -b.llr
+    sat = np.where(b.llr >= 0, 127, -127).astype(b.llr.dtype) if dtype == "i8" else b.llr * 100
+    for name, llr in (("zeros", zeros), ("flipped", flipped), ("saturated", sat)):
+        for L in (1, 4, 32):
+            _say(f"degenerate {name} L={L} {dtype}")
+            g = gpu_decode(code, L, llr, dtype)
+            o = oracle_decode(code, L, llr, dtype)
+            compare(g, o, dtype, f"{name} L={L}")
+
+
+def test_deterministic():
+    code, b = batch(2048, 1723, 32, synth.CRC32_POLY, 4.0, 128, 3.5, 7, "f32")
+    g1 = gpu_decode(code, 32, b.llr, "f32")
+    g2 = gpu_decode(code, 32, b.llr, "f32")
+    for x, y in zip(g1, g2):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_oneshot_entry_point():
+    import torch
+
+    import paper_1505_01466_amd as pk
+
+    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 100, 2.5, 8, "i16")
+    llr = torch.from_numpy(b.llr).cuda()
+    u, ok = pk.decode(code.N, code.K, code.frozen, code.poly, code.r, 8, llr, "i16")
+    torch.cuda.synchronize()
+    o = oracle_decode(code, 8, b.llr, "i16")
+    assert (u.cpu().numpy() == o[0]).all() and (ok.cpu().numpy() == o[1]).all()
