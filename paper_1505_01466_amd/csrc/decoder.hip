@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -103,18 +104,107 @@ template <>
 struct Dom<int8_t> : DomI<127> {};
 
 // ---------------------------------------------------------------------------
-// Kernel arguments and per-workgroup context.
+// 16-byte vector access to LLR stages.
 // ---------------------------------------------------------------------------
 
+DEV uint32_t comp4(const uint4& q, int j) {
+    return j == 0 ? q.x : (j == 1 ? q.y : (j == 2 ? q.z : q.w));
+}
+
+template <typename T>
+struct VecIO;
+
+template <>
+struct VecIO<float> {
+    static constexpr int LOGV = 2;
+    static constexpr int V = 4;
+    static DEV void unpack(const uint4& q, float* o) {
+        o[0] = __uint_as_float(q.x);
+        o[1] = __uint_as_float(q.y);
+        o[2] = __uint_as_float(q.z);
+        o[3] = __uint_as_float(q.w);
+    }
+    static DEV uint4 pack(const float* v) {
+        return make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                          __float_as_uint(v[3]));
+    }
+};
+
+template <>
+struct VecIO<int16_t> {
+    static constexpr int LOGV = 3;
+    static constexpr int V = 8;
+    static DEV void unpack(const uint4& q, int* o) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t x = comp4(q, w);
+            o[2 * w] = ((int)(x << 16)) >> 16;
+            o[2 * w + 1] = ((int)x) >> 16;
+        }
+    }
+    static DEV uint4 pack(const int* v) {
+        uint32_t w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t] = ((uint32_t)v[2 * t] & 0xffffu) | ((uint32_t)v[2 * t + 1] << 16);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+};
+
+template <>
+struct VecIO<int8_t> {
+    static constexpr int LOGV = 4;
+    static constexpr int V = 16;
+    static DEV void unpack(const uint4& q, int* o) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t x = comp4(q, w);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o[4 * w + j] = ((int)(x << (24 - 8 * j))) >> 24;
+        }
+    }
+    static DEV uint4 pack(const int* v) {
+        uint32_t w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            w[t] = ((uint32_t)v[4 * t] & 0xffu) | (((uint32_t)v[4 * t + 1] & 0xffu) << 8) |
+                   (((uint32_t)v[4 * t + 2] & 0xffu) << 16) | ((uint32_t)v[4 * t + 3] << 24);
+        return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Operation records (built on the host) and kernel arguments.
+// ---------------------------------------------------------------------------
+
+// One schedule entry, 8 bytes so that the schedule sits in LDS.
+// meta = type | k << 3 | side << 7 | cand << 8 | in_space << 12 | out_space << 14.
+// Operands (x, y, z):  F, G: LLR stage k, LLR stage k - 1, left partial sums
+// of level k - 1;  Combine: left and right partial sums of level k - 1,
+// output partial sums of level k;  leaves: LLR stage k, output partial sums
+// of level k.  LLR stage offsets are in 16-byte units within a frame's LDS or
+// 256-byte units within its workspace (the space is in meta); partial-sum
+// offsets are in 16-byte units of LDS, or in 256-byte units of the workspace
+// when bit 15 is set.
+struct OpRec {
+    uint16_t meta, x, y, z;
+};
+DEV int op_type(const OpRec& o) { return o.meta & 7; }
+DEV int op_k(const OpRec& o) { return (o.meta >> 3) & 15; }
+DEV int op_side(const OpRec& o) { return (o.meta >> 7) & 1; }
+DEV int op_cand(const OpRec& o) { return (o.meta >> 8) & 15; }
+DEV int op_isp(const OpRec& o) { return (o.meta >> 12) & 3; }
+DEV int op_osp(const OpRec& o) { return (o.meta >> 14) & 3; }
+
 struct KArgs {
-    const uint32_t* ops;  // type | k << 8 | side << 16 | cand << 24
-    const int32_t* tab;   // [a_off | bl_off | br_off], MAXLVL entries each
+    const OpRec* ops;
     const uint64_t* syn;  // N codeword-domain CRC syndromes
     const uint16_t* info_pos;
     uint8_t* ws;
     int64_t ws_frame;
-    int n_ops, N, n, K, L, lL, FW, k_glob, lds_frame, has_crc;
-    int ptrA_off, ptrB_off, pm_off, cpm_off, surv_off, sinfo_off;
+    int n_ops, N, n, K, L, FW, lds_frame, has_crc, sched_lds;
+    int ptrA_off, ptrB_off, pm_off, root_off;
+    // candidate scratch, two copies (consecutive forks alternate)
+    int cpm_off, ckey_off, surv_off, sinfo_off, hd_off, hd_words, scr_stride;
 };
 
 DEV int words_of(int k) { return k >= 5 ? (1 << (k - 5)) : 1; }
@@ -125,155 +215,201 @@ struct Ctx {
     unsigned char* lds;
     uint8_t* wsb;
     const T* llr;
-    const int32_t* tab;
     int64_t f0, F, ws_frame;
-    int lds_frame, N, n, L, lL, FW, k_glob, tid, NT, lane;
-    int ptrA_off, ptrB_off, pm_off, cpm_off, surv_off, sinfo_off;
-    int cur;
+    int lds_frame, N, n, L, FW, tid, NT, lane;
+    int ptrA_off, ptrB_off, pm_off, root_off;
+    int cpm_off, ckey_off, surv_off, sinfo_off, hd_off, hd_words, scr_stride;
+    int cur;  // which copy of the path tables is current
+    int fb;   // which copy of the candidate scratch the next fork uses
 
     DEV unsigned char* fl(int fi) const { return lds + fi * lds_frame; }
-    DEV uint8_t* ptrA(int fi, int buf, int k) const {
-        return fl(fi) + ptrA_off + (buf * MAXLVL + k) * L;
+    // Path -> buffer tables, one 16-byte row per slot (entry k = tree level
+    // k), double-buffered so that a selection can rebuild them from the old
+    // rows.  ptrA maps LLR stages, ptrB left partial sums.
+    DEV uint8_t* rowA(int fi, int buf, int slot) const {
+        return fl(fi) + ptrA_off + ((buf * L + slot) << 4);
     }
-    DEV uint8_t* ptrB(int fi, int buf, int k) const {
-        return fl(fi) + ptrB_off + (buf * MAXLVL + k) * L;
+    DEV uint8_t* rowB(int fi, int buf, int slot) const {
+        return fl(fi) + ptrB_off + ((buf * L + slot) << 4);
     }
-    DEV typename Dom<T>::M* pm(int fi) const {
-        return (typename Dom<T>::M*)(fl(fi) + pm_off);
-    }
-    DEV typename Dom<T>::M* cpm(int fi) const {
-        return (typename Dom<T>::M*)(fl(fi) + cpm_off);
-    }
-    DEV uint16_t* surv(int fi) const { return (uint16_t*)(fl(fi) + surv_off); }
-    DEV uint16_t* sinfo(int fi) const { return (uint16_t*)(fl(fi) + sinfo_off); }
-    DEV uint32_t* bl(int fi, int k, int slot) const {
-        return (uint32_t*)(fl(fi) + tab[MAXLVL + k]) + slot * words_of(k);
-    }
-    DEV uint32_t* br(int fi, int k, int slot) const {
-        return (uint32_t*)(fl(fi) + tab[2 * MAXLVL + k]) + slot * words_of(k);
-    }
-    DEV T* st_lds(int fi, int k, int slot) const {
-        return (T*)(fl(fi) + tab[k]) + (slot << k);
-    }
-    DEV T* st_ws(int fi, int k, int slot) const {
-        return (T*)(wsb + fi * ws_frame + tab[k]) + (slot << k);
+    DEV int srcA(int fi, int k, int slot) const { return rowA(fi, cur, slot)[k]; }
+    DEV int srcB(int fi, int k, int slot) const { return rowB(fi, cur, slot)[k]; }
+    DEV void setA(int fi, int k, int slot) const { rowA(fi, cur, slot)[k] = (uint8_t)slot; }
+    DEV void setB(int fi, int k, int slot) const { rowB(fi, cur, slot)[k] = (uint8_t)slot; }
+    DEV typename Dom<T>::M* pm(int fi) const { return (typename Dom<T>::M*)(fl(fi) + pm_off); }
+    DEV unsigned char* scr(int fi) const { return fl(fi) + fb * scr_stride; }
+    DEV typename Dom<T>::M* cpm(int fi) const { return (typename Dom<T>::M*)(scr(fi) + cpm_off); }
+    DEV uint64_t* ckey(int fi) const { return (uint64_t*)(scr(fi) + ckey_off); }
+    DEV uint16_t* surv(int fi) const { return (uint16_t*)(scr(fi) + surv_off); }
+    DEV uint16_t* sinfo(int fi) const { return (uint16_t*)(scr(fi) + sinfo_off); }
+    DEV uint32_t* hdw(int fi) const { return (uint32_t*)(scr(fi) + hd_off); }
+    // partial-sum words of a slot at level k, stage base offset off
+    DEV uint32_t* bw(int fi, int off, int k, int slot) const {
+        if (off & 0x8000)
+            return (uint32_t*)(wsb + fi * ws_frame + ((off & 0x7fff) << 8)) + slot * words_of(k);
+        return (uint32_t*)(fl(fi) + (off << 4)) + slot * words_of(k);
     }
     DEV const T* chan(int fi) const {
         int64_t f = f0 + fi;
         if (f >= F) f = F - 1;
         return llr + f * N;
     }
-    // Input of a leaf node of size 2^k (the channel row when the root itself
-    // is a leaf).
-    DEV const T* leaf_in(int fi, int k, int slot) const {
-        if (k == n) return chan(fi);
-        if (k >= k_glob) return st_ws(fi, k, slot);
-        return st_lds(fi, k, slot);
-    }
     template <int SP>
-    DEV const T* in_stage(int fi, int k, int slot) const {
-        if constexpr (SP == SP_CH) return chan(fi);
-        else if constexpr (SP == SP_WS) return st_ws(fi, k, slot);
-        else return st_lds(fi, k, slot);
+    DEV T* stage(int fi, int off, int k, int slot) const {
+        if constexpr (SP == SP_WS) return (T*)(wsb + fi * ws_frame + (off << 8)) + (slot << k);
+        else return (T*)(fl(fi) + (off << 4)) + (slot << k);
     }
-    template <int SP>
-    DEV T* out_stage(int fi, int k, int slot) const {
-        if constexpr (SP == SP_WS) return st_ws(fi, k, slot);
-        else return st_lds(fi, k, slot);
+    // Leaf input through a generic pointer (workspace or channel row).
+    DEV const T* leaf_gen(int fi, int off, int k, int slot, int sp) const {
+        if (sp == SP_CH) return chan(fi);
+        return (const T*)(wsb + fi * ws_frame + (off << 8)) + (slot << k);
     }
 };
 
 // ---------------------------------------------------------------------------
-// F and G over all frames, paths and elements of a level-k node.
+// Lane groups.  Between two forking leaves every operation acts on each path
+// on its own (F, G, Combine, Rate-0), so each path instance (frame, path) is
+// given to a group of G lanes inside one wavefront and the whole run of
+// operations proceeds without workgroup barriers: LDS operations of one
+// wavefront complete in issue order, and a wavefront-level fence keeps the
+// compiler from reordering them.
 // ---------------------------------------------------------------------------
 
+struct Grp {
+    int fi, p, g, G;
+    bool valid;
+};
+
+DEV Grp make_grp(int tid, int NT, int FW, int P) {
+    const int I = FW * P;
+    const int NW = NT >> 6;
+    int ipw = (I + NW - 1) / NW;
+    ipw = ipw <= 1 ? 1 : (1 << (32 - __clz(ipw - 1)));
+    if (ipw > 64) ipw = 64;
+    Grp q;
+    q.G = 64 / ipw;
+    const int lg = ilog2u(q.G);
+    const int lane = tid & 63;
+    const int inst = (tid >> 6) * ipw + (lane >> lg);
+    q.valid = inst < I;
+    const int lP = ilog2u(P);
+    q.fi = q.valid ? (inst >> lP) : 0;
+    q.p = q.valid ? (inst & (P - 1)) : 0;
+    q.g = lane & (q.G - 1);
+    return q;
+}
+
+// Orders this lane's earlier memory operations before its later ones as seen
+// by the other lanes of its wavefront.
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// ---------------------------------------------------------------------------
+// Per-path operations.
+// ---------------------------------------------------------------------------
+
+// F / G of one path at a level-k node, eqs. (f) and (g): lane g of the group
+// takes 16-byte chunks g, g + G, ..., up to U of them loaded before any is
+// stored.
 template <typename T, bool IS_G, int ISP, int OSP>
-DEV void op_fg(const Ctx<T>& c, int k, int P) {
+DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
+    using IO = VecIO<T>;
     using D = Dom<T>;
     using A = typename D::A;
-    const int lm = k - 1;
-    const int M = 1 << lm;
-    const int lP = ilog2u(P);
-    const int lpm = lP + lm;
-    const int total = c.FW << lpm;
-    for (int it = c.tid; it < total; it += c.NT) {
-        const int fi = it >> lpm;
-        const int rem = it & ((1 << lpm) - 1);
-        const int p = rem >> lm;
-        const int i = rem & (M - 1);
-        const int src = (ISP == SP_CH) ? 0 : c.ptrA(fi, c.cur, k)[p];
-        const T* in = c.template in_stage<ISP>(fi, k, src);
-        T* out = c.template out_stage<OSP>(fi, k - 1, p);
-        const A x = D::load(in[i]);
-        const A y = D::load(in[i + M]);
-        A v;
-        if constexpr (IS_G) {
-            const uint32_t* b = c.bl(fi, k - 1, c.ptrB(fi, c.cur, k - 1)[p]);
-            const int beta = (b[i >> 5] >> (i & 31)) & 1;
-            v = D::g(x, y, beta);
-        } else {
-            v = D::f(x, y);
+    constexpr int V = IO::V;
+    constexpr int LOGV = IO::LOGV;
+    constexpr int U = 4;
+    if (!q.valid) return;
+    const int M = 1 << (k - 1);
+    const T* in;
+    if constexpr (ISP == SP_CH) in = c.chan(q.fi);
+    else in = c.template stage<ISP>(q.fi, op.x, k, c.srcA(q.fi, k, q.p));
+    T* out = c.template stage<OSP>(q.fi, op.y, k - 1, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.bw(q.fi, op.z, k - 1, c.srcB(q.fi, k - 1, q.p));
+    if (M >= V) {
+        const int nch = M >> LOGV;
+        for (int ch0 = q.g; ch0 < nch; ch0 += q.G * U) {
+            uint4 xq[U], yq[U];
+            uint32_t bb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ch = ch0 + u * q.G;
+                const int chc = ch < nch ? ch : ch0;
+                xq[u] = *(const uint4*)(in + (chc << LOGV));
+                yq[u] = *(const uint4*)(in + M + (chc << LOGV));
+                if constexpr (IS_G) bb[u] = bl[(chc << LOGV) >> 5] >> ((chc << LOGV) & 31);
+                else bb[u] = 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int ch = ch0 + u * q.G;
+                if (ch >= nch) continue;
+                A x[V], y[V], o[V];
+                IO::unpack(xq[u], x);
+                IO::unpack(yq[u], y);
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const A xa = (ISP == SP_CH) ? D::load(x[j]) : x[j];
+                    const A ya = (ISP == SP_CH) ? D::load(y[j]) : y[j];
+                    if constexpr (IS_G) o[j] = D::g(xa, ya, (bb[u] >> j) & 1u);
+                    else o[j] = D::f(xa, ya);
+                }
+                *(uint4*)(out + (ch << LOGV)) = IO::pack(o);
+            }
         }
-        out[i] = (T)v;
+    } else {
+        for (int i = q.g; i < M; i += q.G) {
+            const A x = D::load(in[i]);
+            const A y = D::load(in[i + M]);
+            A v;
+            if constexpr (IS_G) v = D::g(x, y, (bl[i >> 5] >> (i & 31)) & 1u);
+            else v = D::f(x, y);
+            out[i] = (T)v;
+        }
     }
-    const int tp = c.FW << lP;
-    for (int it = c.tid; it < tp; it += c.NT) {
-        const int fi = it >> lP;
-        const int p = it & (P - 1);
-        c.ptrA(fi, c.cur, k - 1)[p] = (uint8_t)p;
-    }
+    if (q.g == 0) c.setA(q.fi, k - 1, q.p);
 }
 
 template <typename T, bool IS_G>
-DEV void op_fg_dispatch(const Ctx<T>& c, int k, int P) {
-    const bool in_ch = (k == c.n);
-    const bool in_ws = !in_ch && k >= c.k_glob;
-    const bool out_ws = (k - 1) >= c.k_glob;
-    if (in_ch) {
-        if (out_ws) op_fg<T, IS_G, SP_CH, SP_WS>(c, k, P);
-        else op_fg<T, IS_G, SP_CH, SP_LDS>(c, k, P);
-    } else if (in_ws) {
-        if (out_ws) op_fg<T, IS_G, SP_WS, SP_WS>(c, k, P);
-        else op_fg<T, IS_G, SP_WS, SP_LDS>(c, k, P);
+DEV void pp_fg_any(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
+    const int isp = op_isp(op);
+    const int osp = op_osp(op);
+    if (isp == SP_LDS) pp_fg<T, IS_G, SP_LDS, SP_LDS>(c, op, k, q);
+    else if (isp == SP_WS) {
+        if (osp == SP_WS) pp_fg<T, IS_G, SP_WS, SP_WS>(c, op, k, q);
+        else pp_fg<T, IS_G, SP_WS, SP_LDS>(c, op, k, q);
     } else {
-        op_fg<T, IS_G, SP_LDS, SP_LDS>(c, k, P);
+        if (osp == SP_WS) pp_fg<T, IS_G, SP_CH, SP_WS>(c, op, k, q);
+        else pp_fg<T, IS_G, SP_CH, SP_LDS>(c, op, k, q);
     }
 }
 
 // Combine, eq. (combine), on bit-packed words: beta_v = (beta_l ^ beta_r, beta_r).
 template <typename T>
-DEV void op_comb(const Ctx<T>& c, int k, int side, int P) {
+DEV void pp_comb(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
+    if (!q.valid) return;
     const int W = words_of(k);
-    const int lw = ilog2u(W);
-    const int lP = ilog2u(P);
-    const int total = c.FW << (lP + lw);
-    for (int it = c.tid; it < total; it += c.NT) {
-        const int fi = it >> (lP + lw);
-        const int p = (it >> lw) & (P - 1);
-        const int w = it & (W - 1);
-        const uint32_t* l = c.bl(fi, k - 1, c.ptrB(fi, c.cur, k - 1)[p]);
-        const uint32_t* r = c.br(fi, k - 1, p);
-        uint32_t v;
-        if (k >= 6) {
-            const int hw = W >> 1;
-            v = (w < hw) ? (l[w] ^ r[w]) : r[w - hw];
-        } else {
-            const int h = 1 << (k - 1);
-            const uint32_t m = (1u << h) - 1u;
-            const uint32_t lv = l[0] & m, rv = r[0] & m;
-            v = (lv ^ rv) | (rv << h);
+    const uint32_t* l = c.bw(q.fi, op.x, k - 1, c.srcB(q.fi, k - 1, q.p));
+    const uint32_t* r = c.bw(q.fi, op.y, k - 1, q.p);
+    uint32_t* o = c.bw(q.fi, op.z, k, q.p);
+    if (k >= 6) {
+        const int hw = W >> 1;
+        for (int w = q.g; w < hw; w += q.G) {
+            const uint32_t lv = l[w], rv = r[w];
+            o[w] = lv ^ rv;
+            o[w + hw] = rv;
         }
-        uint32_t* o = side ? c.br(fi, k, p) : c.bl(fi, k, p);
-        o[w] = v;
+    } else if (q.g == 0) {
+        const int h = 1 << (k - 1);
+        const uint32_t m = (1u << h) - 1u;
+        const uint32_t lv = l[0] & m, rv = r[0] & m;
+        o[0] = (lv ^ rv) | (rv << h);
     }
-    if (side == 0) {
-        const int tp = c.FW << lP;
-        for (int it = c.tid; it < tp; it += c.NT) {
-            const int fi = it >> lP;
-            const int p = it & (P - 1);
-            c.ptrB(fi, c.cur, k)[p] = (uint8_t)p;
-        }
-    }
+    if (side == 0 && q.g == 0) c.setB(q.fi, k, q.p);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +419,9 @@ DEV void op_comb(const Ctx<T>& c, int k, int side, int P) {
 // Candidate flip sets of the SPC decoder over the four least reliable bits
 // m1..m4 (bit t <-> m_{t+1}), relative to the ML word: {}, {1,2}, {1,3},
 // {1,4}, {2,3}, {2,4}, {3,4}, {1,2,3,4} (Sec. III-D).
-__constant__ uint8_t kSpcFlips[8] = {0x0, 0x3, 0x5, 0x9, 0x6, 0xA, 0xC, 0xF};
+// Packed as nibbles: rank r's set is (kSpcFlips >> 4r) & 0xF.
+constexpr uint32_t kSpcFlips = 0xFCA69530u;
+DEV uint32_t spc_flips(int r) { return (kSpcFlips >> (4 * r)) & 0xFu; }
 
 DEV uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 DEV uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
@@ -306,7 +444,7 @@ template <>
 DEV int shfl_xor_s<int>(int v, int m) { return shfl_xor_i(v, m); }
 
 // The 4 smallest of two ascending 4-lists, ascending (bitonic split of a
-// reversed against b, then a 4-element bitonic merge).
+// against reversed b, then a 4-element bitonic merge).
 DEV void merge4(uint64_t* a, const uint64_t* b) {
     const uint64_t l0 = umin64(a[0], b[3]), l1 = umin64(a[1], b[2]);
     const uint64_t l2 = umin64(a[2], b[1]), l3 = umin64(a[3], b[0]);
@@ -318,288 +456,360 @@ DEV void merge4(uint64_t* a, const uint64_t* b) {
     a[3] = umax64(x2, x3);
 }
 
-template <typename T>
-DEV void leaf_rate0(const Ctx<T>& c, int k, int side, int P) {
+DEV void insert4(uint64_t* kk, uint64_t key) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint64_t lo = umin64(kk[q], key);
+        key = umax64(kk[q], key);
+        kk[q] = lo;
+    }
+}
+
+// Visits every element of one path's leaf input: lane g of a group of G lanes
+// takes chunks g, g + G, ... of one 16-byte vector (of single elements when
+// the node is shorter than a vector), two chunks loaded at a time.
+// fn(index, value).
+template <typename T, int ISP, class Fn>
+DEV void leaf_scan(const T* in, int nv, int g, int G, Fn fn) {
+    using IO = VecIO<T>;
+    using D = Dom<T>;
+    using A = typename D::A;
+    if (nv >= IO::V) {
+        const int nch = nv >> IO::LOGV;
+        for (int ch = g; ch < nch; ch += 2 * G) {
+            const int ch2 = ch + G;
+            const uint4 q0 = *(const uint4*)(in + (ch << IO::LOGV));
+            const uint4 q1 = *(const uint4*)(in + ((ch2 < nch ? ch2 : ch) << IO::LOGV));
+            A v[IO::V];
+            IO::unpack(q0, v);
+#pragma unroll
+            for (int j = 0; j < IO::V; ++j)
+                fn((ch << IO::LOGV) + j, (ISP == SP_LDS) ? v[j] : D::load(v[j]));
+            if (ch2 < nch) {
+                IO::unpack(q1, v);
+#pragma unroll
+                for (int j = 0; j < IO::V; ++j)
+                    fn((ch2 << IO::LOGV) + j, (ISP == SP_LDS) ? v[j] : D::load(v[j]));
+            }
+        }
+    } else {
+        for (int i = g; i < nv; i += G) fn(i, D::load(in[i]));
+    }
+}
+
+template <typename T, int ISP>
+DEV const T* leaf_input(const Ctx<T>& c, const OpRec& op, int fi, int k, int slot) {
+    if constexpr (ISP == SP_LDS) return c.template stage<SP_LDS>(fi, op.x, k, slot);
+    else return c.leaf_gen(fi, op.x, k, slot, op_isp(op));
+}
+
+// Hard decisions (eq. (info)) of elements 32w .. 32w + 31 of a leaf input
+// as one word (bit x = element 32w + x; nodes shorter than 32 use the low
+// bits).
+template <typename T, int ISP>
+DEV uint32_t hd_word(const T* in, int w, int nv) {
+    using IO = VecIO<T>;
+    using D = Dom<T>;
+    using A = typename D::A;
+    const T* iw = in + (w << 5);
+    const int nb = nv < 32 ? nv : 32;
+    uint32_t word = 0u;
+    if (nb >= IO::V) {
+        constexpr int NQ = 32 / IO::V;
+        uint4 v4[NQ];
+        const int nq = nb >> IO::LOGV;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+            if (t < nq) v4[t] = *(const uint4*)(iw + (t << IO::LOGV));
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            if (t >= nq) break;
+            A v[IO::V];
+            IO::unpack(v4[t], v);
+#pragma unroll
+            for (int x = 0; x < IO::V; ++x)
+                word |= (D::load(v[x]) < 0 ? 1u : 0u) << ((t << IO::LOGV) + x);
+        }
+    } else {
+        for (int x = 0; x < nb; ++x) word |= (D::load(iw[x]) < 0 ? 1u : 0u) << x;
+    }
+    return word;
+}
+
+// Rate-0 of one path, Sec. III-B: the metric loses the distance of the
+// all-zero word (eq. (rel:frozen-h)); the output is all zeros.
+template <typename T, int ISP>
+DEV void pp_rate0(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
     using D = Dom<T>;
     using A = typename D::A;
     using S = typename D::S;
     const int nv = 1 << k;
-    const int G = nv < 64 ? nv : 64;
-    const int lg = ilog2u(G);
-    const int cnt = nv >> lg;
-    const int lP = ilog2u(P);
-    const int total = c.FW << (lP + lg);
-    const int wave = c.tid >> 6;
-    for (int base = wave * 64; base < total; base += c.NT) {
-        const int it = base + c.lane;
-        const bool act = it < total;
-        const int itc = act ? it : total - 1;
-        const int fi = itc >> (lP + lg);
-        const int p = (itc >> lg) & (P - 1);
-        const int g = itc & (G - 1);
-        const T* in = c.leaf_in(fi, k, c.ptrA(fi, c.cur, k)[p]);
-        S s = 0;
-        for (int t = 0; t < cnt; ++t) {
-            const A v = D::load(in[g + (t << lg)]);
+    const T* in = leaf_input<T, ISP>(c, op, q.fi, k, c.srcA(q.fi, k, q.p));
+    S s = 0;
+    if (q.valid) {
+        leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int, A v) {
             if (v < 0) s += D::widen_abs(v);
-        }
-        for (int m = 1; m < G; m <<= 1) s += shfl_xor_s<S>(s, m);
-        if (act && g == 0) c.pm(fi)[p] = D::sub(c.pm(fi)[p], D::round_pen(s));
+        });
     }
-    const int W = words_of(k);
-    const int lw = ilog2u(W);
-    const int tw = c.FW << (lP + lw);
-    for (int it = c.tid; it < tw; it += c.NT) {
-        const int fi = it >> (lP + lw);
-        const int p = (it >> lw) & (P - 1);
-        const int w = it & (W - 1);
-        (side ? c.br(fi, k, p) : c.bl(fi, k, p))[w] = 0u;
-    }
-    if (side == 0) {
-        const int tp = c.FW << lP;
-        for (int it = c.tid; it < tp; it += c.NT) {
-            c.ptrB(it >> lP, c.cur, k)[it & (P - 1)] = (uint8_t)(it & (P - 1));
-        }
-    }
+    for (int m = 1; m < q.G; m <<= 1) s += shfl_xor_s<S>(s, m);
+    if (!q.valid) return;
+    if (q.g == 0) c.pm(q.fi)[q.p] = D::sub(c.pm(q.fi)[q.p], D::round_pen(s));
+    uint32_t* o = c.bw(q.fi, op.y, k, q.p);
+    for (int w = q.g; w < words_of(k); w += q.G) o[w] = 0u;
+    if (side == 0 && q.g == 0) c.setB(q.fi, k, q.p);
 }
 
-// Forking leaves: repetition, Rate-1 and SPC.  Pass 1 scores the candidates
-// of every source path; pass 2 ranks them; pass 3 writes the survivors'
-// codewords, metrics and buffer indices.
-template <typename T, int TYPE>
-DEV void leaf_fork(Ctx<T>& c, int k, int side, int ccount, int P) {
+// Pass 1 of a forking leaf for one source path: its statistics and the
+// metrics of its candidates, in rank order (the ML candidate first).
+template <typename T, int TYPE, int ISP>
+DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, const Grp& q) {
     using D = Dom<T>;
     using A = typename D::A;
     using S = typename D::S;
     using M = typename D::M;
     const int nv = 1 << k;
-    const int lP = ilog2u(P);
     const int lc = ilog2u(ccount);
+    const int s = q.p;
+    const T* in = leaf_input<T, ISP>(c, op, q.fi, k, c.srcA(q.fi, k, s));
+    M* cp = c.cpm(q.fi) + (s << lc);
+    uint64_t* ck = c.ckey(q.fi) + (s << lc);
+    uint16_t* si = c.sinfo(q.fi) + s * 8;
+    const M pms = c.pm(q.fi)[s];
+    // The source's hard decisions are saved for pass 3: by then another
+    // path may already be writing this LLR stage buffer.
+    if ((TYPE == OP_R1 && k > 0) || TYPE == OP_SPC) {
+        if (q.valid) {
+            uint32_t* hd = c.hdw(q.fi) + s * c.hd_words;
+            for (int w = q.g; w < words_of(k); w += q.G) hd[w] = hd_word<T, ISP>(in, w, nv);
+        }
+    }
+    auto put = [&](int r, M v) {
+        cp[r] = v;
+        ck[r] = ((uint64_t)D::order(v) << 32) | (uint32_t)(0xffff - ((s << lc) + r));
+    };
+    if constexpr (TYPE == OP_REP) {
+        // penalties of the all-zero and all-one words (Sec. III-E)
+        S z = 0, o = 0;
+        if (q.valid) {
+            leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int, A v) {
+                if (v < 0) z += D::widen_abs(v);
+                else o += D::widen_abs(v);
+            });
+        }
+        for (int m = 1; m < q.G; m <<= 1) {
+            z += shfl_xor_s<S>(z, m);
+            o += shfl_xor_s<S>(o, m);
+        }
+        if (q.valid && q.g == 0) {
+            const M zr = D::round_pen(z), orr = D::round_pen(o);
+            const bool one = orr < zr;  // ML word first; equal -> all-zero
+            put(0, D::sub(pms, one ? orr : zr));
+            put(1, D::sub(pms, one ? zr : orr));
+            si[4] = one ? 1 : 0;
+        }
+    } else if constexpr (TYPE == OP_R1) {
+        if (k == 0) {
+            if (q.valid && q.g == 0) {
+                const A v = D::load(in[0]);
+                put(0, pms);
+                put(1, D::sub(pms, D::round_pen(D::widen_abs(v))));
+                si[4] = (v < 0) ? 1 : 0;
+            }
+        } else {
+            // two least reliable positions, ties to the lower index
+            uint64_t k1 = ~0ull, k2 = ~0ull;
+            if (q.valid) {
+                leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
+                    const uint64_t key = ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i;
+                    const uint64_t lo = umin64(k1, key);
+                    k2 = umin64(umax64(k1, key), k2);
+                    k1 = lo;
+                });
+            }
+            for (int m = 1; m < q.G; m <<= 1) {
+                const uint64_t o1 = shfl_xor64(k1, m), o2 = shfl_xor64(k2, m);
+                const uint64_t n1 = umin64(k1, o1);
+                const uint64_t n2 = umin64(umax64(k1, o1), umin64(k2, o2));
+                k1 = n1;
+                k2 = n2;
+            }
+            if (q.valid && q.g == 0) {
+                const S a1 = D::mag_from_key((uint32_t)(k1 >> 32));
+                const S a2 = D::mag_from_key((uint32_t)(k2 >> 32));
+                put(0, pms);
+                put(1, D::sub(pms, D::round_pen(a1)));
+                put(2, D::sub(pms, D::round_pen(a2)));
+                put(3, D::sub(pms, D::round_pen(a1 + a2)));
+                si[0] = (uint16_t)(k1 & 0xffff);
+                si[1] = (uint16_t)(k2 & 0xffff);
+            }
+        }
+    } else {  // OP_SPC
+        uint64_t kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+        int par = 0;
+        if (q.valid) {
+            leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
+                par ^= (v < 0) ? 1 : 0;
+                insert4(kk, ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i);
+            });
+        }
+        for (int m = 1; m < q.G; m <<= 1) {
+            uint64_t ob[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) ob[t] = shfl_xor64(kk[t], m);
+            par ^= shfl_xor_i(par, m);
+            merge4(kk, ob);
+        }
+        if (q.valid && q.g == 0) {
+            // The four positions re-sorted by index (carrying their
+            // reliability rank), so penalties sum in index order.
+            uint32_t idx[4], rk[4];
+            S mag[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                idx[t] = (uint32_t)(kk[t] & 0xffff);
+                mag[t] = D::mag_from_key((uint32_t)(kk[t] >> 32));
+                rk[t] = (uint32_t)t;
+                si[t] = (uint16_t)idx[t];
+            }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+#pragma unroll
+                for (int y = 0; y < 3 - x; ++y) {
+                    const bool sw = idx[y] > idx[y + 1];
+                    const uint32_t i0 = idx[y], i1 = idx[y + 1];
+                    const uint32_t r0 = rk[y], r1 = rk[y + 1];
+                    const S m0 = mag[y], m1 = mag[y + 1];
+                    idx[y] = sw ? i1 : i0;
+                    idx[y + 1] = sw ? i0 : i1;
+                    rk[y] = sw ? r1 : r0;
+                    rk[y + 1] = sw ? r0 : r1;
+                    mag[y] = sw ? m1 : m0;
+                    mag[y + 1] = sw ? m0 : m1;
+                }
+            }
+            si[4] = (uint16_t)par;
+            const uint32_t base_d = par ? 1u : 0u;  // ML flips m1 when parity fails
+            for (int r = 0; r < ccount; ++r) {
+                const uint32_t dm = spc_flips(r) ^ base_d;
+                S pen = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if ((dm >> rk[t]) & 1u) pen += mag[t];
+                put(r, D::sub(pms, D::round_pen(pen)));
+            }
+        }
+    }
+}
+
+template <typename T, int TYPE>
+DEV void pp_fork_score_any(const Ctx<T>& c, const OpRec& op, int k, int cc, const Grp& q) {
+    if (op_isp(op) == SP_LDS) pp_fork_score<T, TYPE, SP_LDS>(c, op, k, cc, q);
+    else pp_fork_score<T, TYPE, SP_WS>(c, op, k, cc, q);
+}
+
+// Candidate selection, Alg. 1, over the whole workgroup: a candidate's rank
+// is the number of candidates of its frame that beat it (larger metric, or
+// equal metric and smaller enumeration index), counted by TP lanes over
+// disjoint slices and summed; ranks 0..L-1 survive, best first.
+template <typename T>
+DEV void select_rank(const Ctx<T>& c, int C, int L) {
+    const int lC = ilog2u(C);
+    int TP = c.NT / (c.FW << lC);
+    TP = TP < 1 ? 1 : (TP > 64 ? 64 : TP);
+    TP = 1 << ilog2u(TP);
+    if (C >= 8 && TP > (C >> 3)) TP = C >> 3;  // slices of at least 8 keys
+    if (C < 8) TP = 1;
+    const int lt = ilog2u(TP);
+    const int span = C >> lt;
+    const int total = c.FW << (lC + lt);
     const int wave = c.tid >> 6;
+    for (int base = wave * 64; base < total; base += c.NT) {
+        const int it = base + c.lane;
+        const bool act = it < total;
+        const int itc = act ? it : total - 1;
+        const int fi = itc >> (lC + lt);
+        const int e = (itc >> lt) & (C - 1);
+        const int t = itc & (TP - 1);
+        const uint64_t* ck = c.ckey(fi);
+        const uint64_t mine = ck[e];
+        const int e0 = t * span;
+        int rank = 0;
+        if (span >= 8) {
+            for (int e2 = e0; e2 < e0 + span; e2 += 8) {
+                uint4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = *(const uint4*)(ck + e2 + 2 * u);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t a0 = ((uint64_t)v[u].y << 32) | v[u].x;
+                    const uint64_t a1 = ((uint64_t)v[u].w << 32) | v[u].z;
+                    rank += (a0 > mine ? 1 : 0) + (a1 > mine ? 1 : 0);
+                }
+            }
+        } else {
+            for (int e2 = e0; e2 < e0 + span; ++e2) rank += ck[e2] > mine ? 1 : 0;
+        }
+        for (int m = 1; m < TP; m <<= 1) rank += shfl_xor_i(rank, m);
+        if (act && t == 0 && rank < L) c.surv(fi)[rank] = (uint16_t)e;
+    }
+}
 
-    // ---- pass 1: per source path statistics and candidate metrics ----
-    {
-        const int G = nv < 64 ? nv : 64;
-        const int lg = ilog2u(G);
-        const int cnt = nv >> lg;
-        const int total = c.FW << (lP + lg);
-        for (int base = wave * 64; base < total; base += c.NT) {
-            const int it = base + c.lane;
-            const bool act = it < total;
-            const int itc = act ? it : total - 1;
-            const int fi = itc >> (lP + lg);
-            const int s = (itc >> lg) & (P - 1);
-            const int g = itc & (G - 1);
-            const T* in = c.leaf_in(fi, k, c.ptrA(fi, c.cur, k)[s]);
-            const M pms = c.pm(fi)[s];
-            M* cp = c.cpm(fi) + (s << lc);
-            uint16_t* si = c.sinfo(fi) + s * 8;
-            if constexpr (TYPE == OP_REP) {
-                // penalties of the all-zero and all-one words (Sec. III-E)
-                S z = 0, o = 0;
-                for (int t = 0; t < cnt; ++t) {
-                    const A v = D::load(in[g + (t << lg)]);
-                    if (v < 0) z += D::widen_abs(v);
-                    else o += D::widen_abs(v);
-                }
-                for (int m = 1; m < G; m <<= 1) {
-                    z += shfl_xor_s<S>(z, m);
-                    o += shfl_xor_s<S>(o, m);
-                }
-                if (act && g == 0) {
-                    const M zr = D::round_pen(z), orr = D::round_pen(o);
-                    const bool one = orr < zr;  // ML word first; equal -> all-zero
-                    cp[0] = D::sub(pms, one ? orr : zr);
-                    cp[1] = D::sub(pms, one ? zr : orr);
-                    si[4] = one ? 1 : 0;
-                }
-            } else if constexpr (TYPE == OP_R1) {
-                if (k == 0) {
-                    if (act) {
-                        const A v = D::load(in[0]);
-                        cp[0] = pms;
-                        cp[1] = D::sub(pms, D::round_pen(D::widen_abs(v)));
-                        si[4] = (v < 0) ? 1 : 0;
-                    }
-                } else {
-                    // two least reliable positions, ties to the lower index
-                    uint64_t k1 = ~0ull, k2 = ~0ull;
-                    for (int t = 0; t < cnt; ++t) {
-                        const int i = g + (t << lg);
-                        const uint64_t key = ((uint64_t)D::mag_key(D::load(in[i])) << 32) | (uint32_t)i;
-                        if (key < k1) {
-                            k2 = k1;
-                            k1 = key;
-                        } else if (key < k2) {
-                            k2 = key;
-                        }
-                    }
-                    for (int m = 1; m < G; m <<= 1) {
-                        const uint64_t o1 = shfl_xor64(k1, m), o2 = shfl_xor64(k2, m);
-                        const uint64_t n1 = umin64(k1, o1);
-                        const uint64_t n2 = umin64(umax64(k1, o1), umin64(k2, o2));
-                        k1 = n1;
-                        k2 = n2;
-                    }
-                    if (act && g == 0) {
-                        const S a1 = D::mag_from_key((uint32_t)(k1 >> 32));
-                        const S a2 = D::mag_from_key((uint32_t)(k2 >> 32));
-                        cp[0] = pms;
-                        cp[1] = D::sub(pms, D::round_pen(a1));
-                        cp[2] = D::sub(pms, D::round_pen(a2));
-                        cp[3] = D::sub(pms, D::round_pen(a1 + a2));
-                        si[0] = (uint16_t)(k1 & 0xffff);
-                        si[1] = (uint16_t)(k2 & 0xffff);
-                    }
-                }
-            } else {  // OP_SPC
-                uint64_t kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-                int par = 0;
-                for (int t = 0; t < cnt; ++t) {
-                    const int i = g + (t << lg);
-                    const A v = D::load(in[i]);
-                    par ^= (v < 0) ? 1 : 0;
-                    uint64_t key = ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint64_t lo = umin64(kk[q], key);
-                        key = umax64(kk[q], key);
-                        kk[q] = lo;
-                    }
-                }
-                for (int m = 1; m < G; m <<= 1) {
-                    uint64_t ob[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) ob[q] = shfl_xor64(kk[q], m);
-                    par ^= shfl_xor_i(par, m);
-                    merge4(kk, ob);
-                }
-                if (act && g == 0) {
-                    // The four positions re-sorted by index (carrying their
-                    // reliability rank), so penalties sum in index order.
-                    uint32_t idx[4], rk[4];
-                    S mag[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        idx[q] = (uint32_t)(kk[q] & 0xffff);
-                        mag[q] = D::mag_from_key((uint32_t)(kk[q] >> 32));
-                        rk[q] = (uint32_t)q;
-                        si[q] = (uint16_t)idx[q];
-                    }
-#pragma unroll
-                    for (int x = 0; x < 3; ++x) {
-#pragma unroll
-                        for (int y = 0; y < 3 - x; ++y) {
-                            const bool sw = idx[y] > idx[y + 1];
-                            const uint32_t i0 = idx[y], i1 = idx[y + 1];
-                            const uint32_t r0 = rk[y], r1 = rk[y + 1];
-                            const S m0 = mag[y], m1 = mag[y + 1];
-                            idx[y] = sw ? i1 : i0;
-                            idx[y + 1] = sw ? i0 : i1;
-                            rk[y] = sw ? r1 : r0;
-                            rk[y + 1] = sw ? r0 : r1;
-                            mag[y] = sw ? m1 : m0;
-                            mag[y + 1] = sw ? m0 : m1;
-                        }
-                    }
-                    si[4] = (uint16_t)par;
-                    const uint32_t base_d = par ? 1u : 0u;  // ML flips m1 when parity fails
-                    for (int r = 0; r < ccount; ++r) {
-                        const uint32_t dm = kSpcFlips[r] ^ base_d;
-                        S pen = 0;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if ((dm >> rk[q]) & 1u) pen += mag[q];
-                        cp[r] = D::sub(pms, D::round_pen(pen));
-                    }
-                }
+// Pass 3 of a forking leaf for one destination slot j: its metric, its path
+// tables (a copy of its source's, sharing every stage buffer), and its
+// codeword (the source's hard decisions with the candidate's flips).
+template <typename T, int TYPE>
+DEV void pp_fork_emit(Ctx<T>& c, int k, int side, int ccount, bool prune, int b_out,
+                      const Grp& q) {
+    if (!q.valid) return;
+    const int nv = 1 << k;
+    const int lc = ilog2u(ccount);
+    const int j = q.p;
+    const int e = prune ? c.surv(q.fi)[j] : j;
+    const int s = e >> lc;
+    const int r = e & (ccount - 1);
+    const uint16_t* si = c.sinfo(q.fi) + s * 8;
+    const int W = words_of(k);
+    const uint32_t full = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
+    const uint32_t* hd = c.hdw(q.fi) + s * c.hd_words;
+    uint32_t* o = c.bw(q.fi, b_out, k, j);
+    for (int w = q.g; w < W; w += q.G) {
+        uint32_t word;
+        if (TYPE == OP_REP || (TYPE == OP_R1 && k == 0)) {
+            word = ((si[4] ^ r) & 1) ? full : 0u;
+        } else {
+            word = hd[w];
+            uint32_t dm;
+            if constexpr (TYPE == OP_R1) dm = (uint32_t)r;
+            else dm = spc_flips(r) ^ (si[4] ? 1u : 0u);
+            const int nflip = (TYPE == OP_R1) ? 2 : 4;
+            for (int t = 0; t < nflip; ++t) {
+                const int pos = (int)si[t] - (w << 5);
+                if (((dm >> t) & 1u) && pos >= 0 && pos < 32) word ^= 1u << pos;
             }
         }
+        o[w] = word;
     }
-    __syncthreads();
+    if (q.g == 0) {
+        const int nxt = c.cur ^ 1;
+        *(uint4*)c.rowA(q.fi, nxt, j) = *(const uint4*)c.rowA(q.fi, c.cur, s);
+        *(uint4*)c.rowB(q.fi, nxt, j) = *(const uint4*)c.rowB(q.fi, c.cur, s);
+        if (side == 0) c.rowB(q.fi, nxt, j)[k] = (uint8_t)j;
+        c.pm(q.fi)[j] = c.cpm(q.fi)[e];
+    }
+}
 
-    // ---- pass 2: rank when candidates must be dropped ----
-    const int C = P << lc;
-    const int lC = lP + lc;
-    const int L = c.L;
-    const bool prune = C > L;
-    if (prune) {
-        const int total = c.FW << lC;
-        for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it >> lC;
-            const int e = it & (C - 1);
-            const M* cp = c.cpm(fi);
-            const uint64_t mine = ((uint64_t)D::order(cp[e]) << 32) | (uint32_t)(0xffff - e);
-            int rank = 0;
-            for (int e2 = 0; e2 < C; ++e2) {
-                const uint64_t other = ((uint64_t)D::order(cp[e2]) << 32) | (uint32_t)(0xffff - e2);
-                rank += other > mine ? 1 : 0;
-            }
-            if (rank < L) c.surv(fi)[rank] = (uint16_t)e;
-        }
-        __syncthreads();
-    }
-
-    // ---- pass 3: survivors ----
-    const int Pn = prune ? L : C;
-    const int lPn = ilog2u(Pn);
-    const int nxt = c.cur ^ 1;
-    {
-        const int levels = c.n + 1;
-        const int total = c.FW * Pn * levels;
-        for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it / (Pn * levels);
-            const int rem = it - fi * (Pn * levels);
-            const int j = rem / levels;
-            const int lv = rem - j * levels;
-            const int e = prune ? c.surv(fi)[j] : j;
-            const int s = e >> lc;
-            c.ptrA(fi, nxt, lv)[j] = c.ptrA(fi, c.cur, lv)[s];
-            c.ptrB(fi, nxt, lv)[j] =
-                (lv == k && side == 0) ? (uint8_t)j : c.ptrB(fi, c.cur, lv)[s];
-            if (lv == 0) c.pm(fi)[j] = c.cpm(fi)[e];
-        }
-    }
-    {
-        // codeword bits, assembled into words with a wave ballot
-        const int total = c.FW << (lPn + k);
-        for (int base = wave * 64; base < total; base += c.NT) {
-            const int it = base + c.lane;
-            const bool act = it < total;
-            const int itc = act ? it : total - 1;
-            const int fi = itc >> (lPn + k);
-            const int j = (itc >> k) & (Pn - 1);
-            const int i = itc & (nv - 1);
-            const int e = prune ? c.surv(fi)[j] : j;
-            const int s = e >> lc;
-            const int r = e & (ccount - 1);
-            const uint16_t* si = c.sinfo(fi) + s * 8;
-            int bit;
-            if constexpr (TYPE == OP_REP) {
-                bit = (si[4] ^ r) & 1;
-            } else {
-                if (TYPE == OP_R1 && k == 0) {
-                    bit = (si[4] ^ r) & 1;
-                } else {
-                    const T* in = c.leaf_in(fi, k, c.ptrA(fi, c.cur, k)[s]);
-                    bit = (D::load(in[i]) < 0) ? 1 : 0;
-                    uint32_t dm;
-                    if constexpr (TYPE == OP_R1) dm = (uint32_t)r;
-                    else dm = kSpcFlips[r] ^ (si[4] ? 1u : 0u);
-                    const int nq = (TYPE == OP_R1) ? 2 : 4;
-                    for (int q = 0; q < nq; ++q)
-                        if (((dm >> q) & 1u) && i == si[q]) bit ^= 1;
-                }
-            }
-            const uint64_t bal = __ballot(act && bit);
-            if (act && (i & 31) == 0) {
-                const uint32_t mask = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
-                const uint32_t wv = (uint32_t)(bal >> c.lane) & mask;
-                (side ? c.br(fi, k, j) : c.bl(fi, k, j))[i >> 5] = wv;
-            }
-        }
-    }
-    c.cur = nxt;
+// Pass 3 of the pending fork described by op.
+template <typename T>
+DEV void pp_emit_pending(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
+    const int type = op_type(op);
+    const int k = op_k(op), side = op_side(op);
+    const int cc = op_cand(op);
+    if (type == OP_REP) pp_fork_emit<T, OP_REP>(c, k, side, cc, prune, op.y, q);
+    else if (type == OP_R1) pp_fork_emit<T, OP_R1>(c, k, side, cc, prune, op.y, q);
+    else pp_fork_emit<T, OP_SPC>(c, k, side, cc, prune, op.y, q);
+    c.cur ^= 1;  // path tables now in the other buffer
+    c.fb ^= 1;   // the next fork uses the other candidate scratch
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +820,6 @@ template <typename T>
 DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t* crc_ok,
                 void* pm_out) {
     using D = Dom<T>;
-    using M = typename D::M;
     const int n = c.n;
     const int W = words_of(n);
     const int lP = ilog2u(P);
@@ -628,16 +837,18 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
             const int fi = itc >> (lP + lg);
             const int j = (itc >> lg) & (P - 1);
             const int g = itc & (G - 1);
-            const uint32_t* x = c.br(fi, n, j);
+            const uint32_t* x = c.bw(fi, c.root_off, n, j);
             uint64_t acc = 0;
             if (a.has_crc) {
+                const int nb = c.N < 32 ? c.N : 32;
                 for (int t = 0; t < cnt; ++t) {
                     const int w = g + (t << lg);
-                    uint32_t v = x[w];
-                    while (v) {
-                        const int b = __ffs(v) - 1;
-                        v &= v - 1;
-                        acc ^= a.syn[(w << 5) + b];
+                    const uint32_t v = x[w];
+                    const uint64_t* sy = a.syn + (w << 5);
+#pragma unroll 8
+                    for (int b = 0; b < nb; ++b) {
+                        const uint64_t tv = sy[b];
+                        acc ^= ((v >> b) & 1u) ? tv : 0ull;
                     }
                 }
                 for (int m = 1; m < G; m <<= 1) acc ^= shfl_xor64(acc, m);
@@ -673,11 +884,12 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
     __syncthreads();
     // u = x G_N on the chosen codeword, in place: bits within words ...
     {
-        const int total = c.FW * W;
+        const int lw = ilog2u(W);
+        const int total = c.FW << lw;
         for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it / W;
-            const int w = it - fi * W;
-            uint32_t* x = c.br(fi, n, c.sinfo(fi)[0]);
+            const int fi = it >> lw;
+            const int w = it & (W - 1);
+            uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
             uint32_t v = x[w];
             v ^= (v >> 1) & 0x55555555u;
             v ^= (v >> 2) & 0x33333333u;
@@ -690,12 +902,13 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
     // ... then across words
     for (int sw = 1; sw < W; sw <<= 1) {
         __syncthreads();
-        const int total = c.FW * W;
+        const int lw = ilog2u(W);
+        const int total = c.FW << lw;
         for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it / W;
-            const int w = it - fi * W;
+            const int fi = it >> lw;
+            const int w = it & (W - 1);
             if (w & sw) continue;
-            uint32_t* x = c.br(fi, n, c.sinfo(fi)[0]);
+            uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
             x[w] ^= x[w + sw];
         }
     }
@@ -708,7 +921,7 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
             const int t = it - fi * K;
             const int64_t f = c.f0 + fi;
             if (f >= c.F) continue;
-            const uint32_t* x = c.br(fi, n, c.sinfo(fi)[0]);
+            const uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
             const int p = a.info_pos[t];
             u_hat[f * K + t] = (uint8_t)((x[p >> 5] >> (p & 31)) & 1u);
         }
@@ -728,25 +941,39 @@ __global__ void __launch_bounds__(1024)
     c.lds = lds;
     c.wsb = a.ws + (int64_t)blockIdx.x * a.FW * a.ws_frame;
     c.llr = llr;
-    c.tab = a.tab;
     c.F = F;
     c.ws_frame = a.ws_frame;
     c.lds_frame = a.lds_frame;
     c.N = a.N;
     c.n = a.n;
     c.L = a.L;
-    c.lL = a.lL;
     c.FW = a.FW;
-    c.k_glob = a.k_glob;
     c.tid = threadIdx.x;
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
     c.ptrA_off = a.ptrA_off;
     c.ptrB_off = a.ptrB_off;
     c.pm_off = a.pm_off;
+    c.root_off = a.root_off;
     c.cpm_off = a.cpm_off;
+    c.ckey_off = a.ckey_off;
     c.surv_off = a.surv_off;
     c.sinfo_off = a.sinfo_off;
+    c.hd_off = a.hd_off;
+    c.hd_words = a.hd_words;
+    c.scr_stride = a.scr_stride;
+    c.fb = 0;
+
+    // The schedule is read from LDS: one broadcast read per operation,
+    // issued while the previous operation runs.
+    // (Schedules too long for LDS are read from global memory instead.)
+    const OpRec* sched = a.ops;
+    if (a.sched_lds) {
+        OpRec* s = (OpRec*)(lds + a.FW * a.lds_frame);
+        for (int i = c.tid; i < a.n_ops; i += c.NT) s[i] = a.ops[i];
+        sched = s;
+    }
+    __syncthreads();
 
     for (int64_t f0 = (int64_t)blockIdx.x * a.FW; f0 < F; f0 += (int64_t)gridDim.x * a.FW) {
         c.f0 = f0;
@@ -754,40 +981,67 @@ __global__ void __launch_bounds__(1024)
         for (int fi = c.tid; fi < c.FW; fi += c.NT) c.pm(fi)[0] = 0;
         __syncthreads();
         int P = 1;
+        Grp q = make_grp(c.tid, c.NT, c.FW, P);
+        c.fb = 0;
+        // a fork whose survivors still have to be written (pass 3)
+        int pend = 0;
+        OpRec pop{};
+        int pprune = 0;
+        OpRec nop = sched[0];
         for (int oi = 0; oi < a.n_ops; ++oi) {
-            const uint32_t op = a.ops[oi];
-            const int type = op & 0xff;
-            const int k = (op >> 8) & 0xff;
-            const int side = (op >> 16) & 0xff;
-            const int cc = (int)(op >> 24);
+            OpRec op;
+            op.meta = (uint16_t)__builtin_amdgcn_readfirstlane(nop.meta);
+            op.x = (uint16_t)__builtin_amdgcn_readfirstlane(nop.x);
+            op.y = (uint16_t)__builtin_amdgcn_readfirstlane(nop.y);
+            op.z = (uint16_t)__builtin_amdgcn_readfirstlane(nop.z);
+            nop = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
+            const int type = op_type(op);
+            const int k = op_k(op);
+            const int side = op_side(op);
+            const int cc = op_cand(op);
+            if (pend) {
+                pp_emit_pending<T>(c, pop, pprune, q);
+                pend = 0;
+                wave_sync();
+            }
             switch (type) {
                 case OP_F:
-                    op_fg_dispatch<T, false>(c, k, P);
+                    pp_fg_any<T, false>(c, op, k, q);
                     break;
                 case OP_G:
-                    op_fg_dispatch<T, true>(c, k, P);
+                    pp_fg_any<T, true>(c, op, k, q);
                     break;
                 case OP_COMB:
-                    op_comb<T>(c, k, side, P);
+                    pp_comb<T>(c, op, k, side, q);
                     break;
                 case OP_R0:
-                    leaf_rate0<T>(c, k, side, P);
+                    if (op_isp(op) == SP_LDS) pp_rate0<T, SP_LDS>(c, op, k, side, q);
+                    else pp_rate0<T, SP_WS>(c, op, k, side, q);
                     break;
-                case OP_REP:
-                    leaf_fork<T, OP_REP>(c, k, side, cc, P);
-                    P = min(c.L, P * cc);
+                default: {
+                    // a forking leaf: score, select across the workgroup, and
+                    // leave the survivors to be written by their new owners
+                    if (type == OP_REP) pp_fork_score_any<T, OP_REP>(c, op, k, cc, q);
+                    else if (type == OP_R1) pp_fork_score_any<T, OP_R1>(c, op, k, cc, q);
+                    else pp_fork_score_any<T, OP_SPC>(c, op, k, cc, q);
+                    const int C = P * cc;
+                    pprune = C > c.L;
+                    __syncthreads();
+                    if (pprune) {
+                        select_rank<T>(c, C, c.L);
+                        __syncthreads();
+                    }
+                    P = pprune ? c.L : C;
+                    q = make_grp(c.tid, c.NT, c.FW, P);
+                    pend = 1;
+                    pop = op;
                     break;
-                case OP_R1:
-                    leaf_fork<T, OP_R1>(c, k, side, cc, P);
-                    P = min(c.L, P * cc);
-                    break;
-                default:
-                    leaf_fork<T, OP_SPC>(c, k, side, cc, P);
-                    P = min(c.L, P * cc);
-                    break;
+                }
             }
-            __syncthreads();
+            wave_sync();
         }
+        if (pend) pp_emit_pending<T>(c, pop, pprune, q);
+        __syncthreads();
         finish<T>(c, a, P, u_hat, crc_ok, pm_out);
         __syncthreads();
     }
@@ -810,13 +1064,12 @@ struct pscl_plan {
     uint64_t poly = 0;
     int device = 0;
     std::vector<SchedOp> sched;
-    uint32_t* d_ops = nullptr;
-    int32_t* d_tab = nullptr;
+    OpRec* d_ops = nullptr;
     uint64_t* d_syn = nullptr;
     uint16_t* d_info = nullptr;
     uint8_t* d_ws = nullptr;
     KArgs args{};
-    int NT = 256, FW = 1, grid_max = 0, lds_bytes = 0;
+    int NT = 256, FW = 1, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int64_t ws_bytes = 0;
     const void* kernel = nullptr;
 };
@@ -842,42 +1095,110 @@ const void* kernel_for(int dtype) {
     }
 }
 
-// Per-frame LDS layout for a given first global stage; returns bytes.
-int layout(pscl_plan* p, int k_glob, int32_t* tab, KArgs& a, int64_t* ws_frame) {
+// Per-frame layout for a given first global stage.  LLR stages below k_glob
+// and all partial sums, path tables and candidate scratch live in LDS; LLR
+// stages k_glob..n-1 live in the workspace.  Returns the LDS bytes per frame.
+struct Layout {
+    int a_off[MAXLVL];  // LLR stage offsets (LDS or workspace)
+    int bl_off[MAXLVL], br_off[MAXLVL];
+    int64_t ws_frame;
+};
+
+int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     const int L = p->L, n = p->n, es = elem_size(p->dtype);
     int off = 0;
     int64_t woff = 0;
-    for (int k = 0; k < MAXLVL; ++k) tab[k] = 0;
+    for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
     for (int k = 0; k < n; ++k) {
         const int bytes = L * (1 << k) * es;
         if (k < k_glob) {
-            tab[k] = off;
+            lay.a_off[k] = off;
             off = align16(off + bytes);
         } else {
-            tab[k] = (int32_t)woff;
+            lay.a_off[k] = (int32_t)woff;
             woff += (bytes + 255) & ~255;
         }
     }
+    // partial sums of level k sit in LDS when k < k_glob, else in the
+    // workspace (offset flagged with bit 15)
     for (int k = 0; k <= n; ++k) {
-        tab[MAXLVL + k] = off;
-        off = align16(off + L * words_host(k) * 4);
-        tab[2 * MAXLVL + k] = off;
-        off = align16(off + L * words_host(k) * 4);
+        const int bytes = L * words_host(k) * 4;
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && k == n) continue;  // the root is never a left child
+            int val;
+            if (k < k_glob) {
+                val = off >> 4;
+                off = align16(off + bytes);
+            } else {
+                val = 0x8000 | (int)(woff >> 8);
+                woff += (bytes + 255) & ~255;
+            }
+            (side == 0 ? lay.bl_off : lay.br_off)[k] = val;
+        }
     }
     a.ptrA_off = off;
-    off = align16(off + 2 * MAXLVL * L);
+    off = align16(off + 2 * 16 * L);
     a.ptrB_off = off;
-    off = align16(off + 2 * MAXLVL * L);
+    off = align16(off + 2 * 16 * L);
     a.pm_off = off;
     off = align16(off + 4 * L);
-    a.cpm_off = off;
-    off = align16(off + 4 * 8 * L);
-    a.surv_off = off;
-    off = align16(off + 2 * 8 * L);
-    a.sinfo_off = off;
-    off = align16(off + 16 * 8 * L);
-    *ws_frame = woff;
+    // candidate scratch (two copies, scr_stride apart): metrics and ranking
+    // keys of up to 8 candidates per path, survivors, per-source statistics
+    // and the sources' hard decisions
+    int hd_words = 1;
+    for (const SchedOp& s : p->sched)
+        if (s.type == OP_R1 || s.type == OP_SPC) hd_words = std::max(hd_words, words_host(s.k));
+    const int base = off;
+    int so = 0;
+    a.cpm_off = base + so;
+    so = align16(so + 4 * 8 * L);
+    a.ckey_off = base + so;
+    so = align16(so + 8 * 8 * L);
+    a.surv_off = base + so;
+    so = align16(so + 2 * 8 * L);
+    a.sinfo_off = base + so;
+    so = align16(so + 16 * L);
+    a.hd_off = base + so;
+    so = align16(so + 4 * hd_words * L);
+    a.hd_words = hd_words;
+    a.scr_stride = so;
+    off = base + 2 * so;
+    a.root_off = lay.br_off[n];
+    lay.ws_frame = woff;
     return off;
+}
+
+// Operation records: the schedule with every operand offset resolved.
+// LLR stage offsets: LDS in 16-byte units, workspace in 256-byte units.
+static uint16_t unit_off(int off, bool ws) { return (uint16_t)(ws ? (off >> 8) : (off >> 4)); }
+
+std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glob) {
+    const int n = p->n;
+    auto space = [&](int k) { return k == n ? SP_CH : (k >= k_glob ? SP_WS : SP_LDS); };
+    std::vector<OpRec> out;
+    for (const SchedOp& s : p->sched) {
+        OpRec r{};
+        const int k = s.k;
+        int isp = space(k), osp = SP_LDS;
+        if (s.type == OP_F || s.type == OP_G) {
+            osp = (k - 1) >= k_glob ? SP_WS : SP_LDS;
+            r.x = k < n ? unit_off(lay.a_off[k], isp == SP_WS) : 0;
+            r.y = unit_off(lay.a_off[k - 1], osp == SP_WS);
+            r.z = (uint16_t)lay.bl_off[k - 1];
+        } else if (s.type == OP_COMB) {
+            isp = SP_LDS;
+            r.x = (uint16_t)lay.bl_off[k - 1];
+            r.y = (uint16_t)lay.br_off[k - 1];
+            r.z = (uint16_t)(s.side ? lay.br_off[k] : lay.bl_off[k]);
+        } else {
+            r.x = k < n ? unit_off(lay.a_off[k], isp == SP_WS) : 0;
+            r.y = (uint16_t)(s.side ? lay.br_off[k] : lay.bl_off[k]);
+        }
+        r.meta = (uint16_t)((uint32_t)s.type | ((uint32_t)k << 3) | ((uint32_t)s.side << 7) |
+                            ((uint32_t)s.cand << 8) | ((uint32_t)isp << 12) | ((uint32_t)osp << 14));
+        out.push_back(r);
+    }
+    return out;
 }
 
 }  // namespace
@@ -926,7 +1247,6 @@ void pscl_plan_destroy(pscl_plan* p) {
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_ops);
-    (void)hipFree(p->d_tab);
     (void)hipFree(p->d_syn);
     (void)hipFree(p->d_info);
     (void)hipFree(p->d_ws);
@@ -968,26 +1288,54 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     }
 
     // Layout: keep as many low stages in LDS as the per-workgroup budget
-    // allows; larger stages go to the global workspace.
-    const int lds_cap = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
-    int32_t tab[3 * MAXLVL];
+    // allows; larger stages go to the global workspace.  The budget trades
+    // LDS per frame (stages kept on chip) against frames resident per CU.
+    const int lds_hw = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
+    int lds_cap = std::min(lds_hw, 20 * 1024);
+    if (const char* e = getenv("PSCL_LDS_BUDGET")) lds_cap = std::max(4096, std::min(lds_hw, atoi(e)));
+    Layout lay;
     KArgs a{};
-    int64_t wsf = 0;
-    int k_glob = p->n;
-    int bytes = layout(p, k_glob, tab, a, &wsf);
-    while (bytes > lds_cap && k_glob > 0) {
+    int k_glob = p->n + 1;
+    int bytes = layout(p, k_glob, lay, a);
+    // The schedule goes to LDS when it is short (at most 16 KiB).
+    const int sched_all = align16((int)p->sched.size() * (int)sizeof(OpRec));
+    const int sched_need = sched_all <= 16384 ? sched_all : 0;
+    while (bytes + sched_need > lds_cap && k_glob > 0) {
         --k_glob;
-        bytes = layout(p, k_glob, tab, a, &wsf);
+        bytes = layout(p, k_glob, lay, a);
     }
-    if (bytes > lds_cap) {
+    if (bytes + sched_need > lds_cap && lds_cap < lds_hw) {
+        // the requested budget is too small for this code: use the hardware cap
+        lds_cap = lds_hw;
+        k_glob = p->n + 1;
+        bytes = layout(p, k_glob, lay, a);
+        while (bytes + sched_need > lds_cap && k_glob > 0) {
+            --k_glob;
+            bytes = layout(p, k_glob, lay, a);
+        }
+    }
+    if (bytes + sched_need > lds_cap) {
         delete p;
         return PSCL_E_UNSUPPORTED;
     }
-    // Frames per workgroup: fill up to a quarter of the LDS budget, at most 8.
+    const int64_t wsf = lay.ws_frame;
+    // Frames per workgroup: lockstep frames share each operation's barrier;
+    // fill up to a quarter of the LDS budget, at most 8.
+    const int sched_bytes = sched_need;
     int FW = std::max(1, std::min(8, (lds_cap / 4) / bytes));
+    while (FW > 1 && bytes * FW + sched_bytes > lds_cap) --FW;
     p->FW = FW;
-    p->NT = 256;
-    p->lds_bytes = bytes * FW;
+    p->lds_bytes = bytes * FW + sched_bytes;
+    // Threads: with one resident workgroup per CU use 1024 threads (16
+    // waves) so that memory latency overlaps across waves; otherwise fewer.
+    // Few waves per frame: every schedule operation costs each of them its
+    // control overhead, and more resident frames per CU hide the latency of
+    // each frame's dependent chain better than more waves per frame.
+    p->NT = 128;
+    if (const char* e = getenv("PSCL_THREADS")) {
+        const int t = atoi(e);
+        if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) p->NT = t;
+    }
     p->kernel = kernel_for(dtype);
 
     hipError_t e = hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1002,12 +1350,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     p->grid_max = occ * prop.multiProcessorCount;
     p->ws_bytes = wsf * FW * (int64_t)p->grid_max;
 
-    std::vector<uint32_t> ops(p->sched.size());
-    for (size_t i = 0; i < ops.size(); ++i) {
-        const SchedOp& s = p->sched[i];
-        ops[i] = (uint32_t)s.type | ((uint32_t)s.k << 8) | ((uint32_t)s.side << 16) |
-                 ((uint32_t)s.cand << 24);
-    }
+    std::vector<OpRec> ops = make_records(p, lay, k_glob);
     std::vector<uint64_t> syn(N, 0);
     if (crc_len > 0) syn = crc_codeword_table(N, frozen_mask, crc_poly, crc_len);
     std::vector<uint16_t> info;
@@ -1015,14 +1358,13 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
         if (!frozen_mask[i]) info.push_back((uint16_t)i);
 
     pscl_status st = PSCL_OK;
-    auto up = [&](void** dst, const void* src, size_t n) {
+    auto up = [&](void** dst, const void* src, size_t nbytes) {
         if (st != PSCL_OK) return;
-        hipError_t err = hipMalloc(dst, std::max<size_t>(n, 16));
-        if (err == hipSuccess && n) err = hipMemcpy(*dst, src, n, hipMemcpyHostToDevice);
+        hipError_t err = hipMalloc(dst, std::max<size_t>(nbytes, 16));
+        if (err == hipSuccess && nbytes) err = hipMemcpy(*dst, src, nbytes, hipMemcpyHostToDevice);
         st = hip_status(err);
     };
-    up((void**)&p->d_ops, ops.data(), ops.size() * 4);
-    up((void**)&p->d_tab, tab, sizeof(tab));
+    up((void**)&p->d_ops, ops.data(), ops.size() * sizeof(OpRec));
     up((void**)&p->d_syn, syn.data(), syn.size() * 8);
     up((void**)&p->d_info, info.data(), info.size() * 2);
     if (st == PSCL_OK && p->ws_bytes > 0) st = hip_status(hipMalloc((void**)&p->d_ws, p->ws_bytes));
@@ -1032,7 +1374,6 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     }
 
     a.ops = p->d_ops;
-    a.tab = p->d_tab;
     a.syn = p->d_syn;
     a.info_pos = p->d_info;
     a.ws = p->d_ws;
@@ -1042,13 +1383,11 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     a.n = p->n;
     a.K = K;
     a.L = L;
-    int lL = 0;
-    while ((1 << lL) < L) ++lL;
-    a.lL = lL;
     a.FW = FW;
-    a.k_glob = k_glob;
     a.lds_frame = bytes;
+    p->k_glob = k_glob;
     a.has_crc = crc_len > 0 ? 1 : 0;
+    a.sched_lds = sched_need > 0 ? 1 : 0;
     p->args = a;
     *out = p;
     return PSCL_OK;
@@ -1062,7 +1401,7 @@ pscl_status pscl_plan_info(const pscl_plan* p, int* frames_per_wg, int* threads,
     if (workgroups) *workgroups = p->grid_max;
     if (lds_bytes) *lds_bytes = p->lds_bytes;
     if (workspace_bytes) *workspace_bytes = p->ws_bytes;
-    if (first_global_stage) *first_global_stage = p->args.k_glob;
+    if (first_global_stage) *first_global_stage = p->k_glob;
     return PSCL_OK;
 }
 
@@ -1071,6 +1410,7 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     if (!p || F < 0) return PSCL_E_INVALID;
     if (F == 0) return PSCL_OK;
     if (!llr || !u_hat) return PSCL_E_INVALID;
+    if (((uintptr_t)llr & 15u) != 0) return PSCL_E_INVALID;  // 16-byte vector loads
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return PSCL_E_HIP;
     const int64_t groups = (F + p->FW - 1) / p->FW;
