@@ -176,15 +176,16 @@ struct VecIO<int8_t> {
 // Operation records (built on the host) and kernel arguments.
 // ---------------------------------------------------------------------------
 
-// One schedule entry, 8 bytes so that the schedule sits in LDS.
+// One schedule entry, 8 bytes so that the schedule can sit in LDS.
 // meta = type | k << 3 | side << 7 | cand << 8 | in_space << 12 | out_space << 14.
-// Operands (x, y, z):  F, G: LLR stage k, LLR stage k - 1, left partial sums
-// of level k - 1;  Combine: left and right partial sums of level k - 1,
-// output partial sums of level k;  leaves: LLR stage k, output partial sums
-// of level k.  LLR stage offsets are in 16-byte units within a frame's LDS or
-// 256-byte units within its workspace (the space is in meta); partial-sum
-// offsets are in 16-byte units of LDS, or in 256-byte units of the workspace
-// when bit 15 is set.
+// Operands (x, y, z) and spaces:
+//   F, G:     x = LLR stage k (in_space), y = LLR stage k - 1 (out_space),
+//             z = left partial sums of level k - 1 (out_space);
+//   Combine:  x, y = left, right partial sums of level k - 1 (in_space),
+//             z = output partial sums of level k (out_space);
+//   leaves:   x = LLR stage k (in_space), y = output partial sums of level k
+//             (out_space).
+// Offsets are in 16-byte units in LDS and 256-byte units in the workspace.
 struct OpRec {
     uint16_t meta, x, y, z;
 };
@@ -200,101 +201,85 @@ struct KArgs {
     const uint64_t* syn;  // N codeword-domain CRC syndromes
     const uint16_t* info_pos;
     uint8_t* ws;
-    int64_t ws_frame;
-    int n_ops, N, n, K, L, FW, lds_frame, has_crc, sched_lds;
-    int ptrA_off, ptrB_off, pm_off, root_off;
-    // candidate scratch, two copies (consecutive forks alternate)
-    int cpm_off, ckey_off, surv_off, sinfo_off, hd_off, hd_words, scr_stride;
+    int64_t ws_frame;  // workspace bytes per workgroup
+    int n_ops, N, n, K, L, has_crc;
+    int ptrA_off, ptrB_off, pm_off, root_off, root_sp;
+    // candidate scratch
+    int cpm_off, ckey_off, surv_off, sinfo_off;
 };
 
 DEV int words_of(int k) { return k >= 5 ? (1 << (k - 5)) : 1; }
 DEV int ilog2u(unsigned v) { return 31 - __clz(v); }
 
+// Per-workgroup view of one frame's decoder state.
 template <typename T>
 struct Ctx {
     unsigned char* lds;
     uint8_t* wsb;
-    const T* llr;
-    int64_t f0, F, ws_frame;
-    int lds_frame, N, n, L, FW, tid, NT, lane;
-    int ptrA_off, ptrB_off, pm_off, root_off;
-    int cpm_off, ckey_off, surv_off, sinfo_off, hd_off, hd_words, scr_stride;
+    const T* chan;  // the frame's channel LLRs
+    int N, n, L, tid, NT, lane;
+    int ptrA_off, ptrB_off, pm_off;
+    int cpm_off, ckey_off, surv_off, sinfo_off;
     int cur;  // which copy of the path tables is current
-    int fb;   // which copy of the candidate scratch the next fork uses
 
-    DEV unsigned char* fl(int fi) const { return lds + fi * lds_frame; }
     // Path -> buffer tables, one 16-byte row per slot (entry k = tree level
     // k), double-buffered so that a selection can rebuild them from the old
     // rows.  ptrA maps LLR stages, ptrB left partial sums.
-    DEV uint8_t* rowA(int fi, int buf, int slot) const {
-        return fl(fi) + ptrA_off + ((buf * L + slot) << 4);
+    DEV uint8_t* rowA(int buf, int slot) const { return lds + ptrA_off + ((buf * L + slot) << 4); }
+    DEV uint8_t* rowB(int buf, int slot) const { return lds + ptrB_off + ((buf * L + slot) << 4); }
+    DEV int srcA(int k, int slot) const { return rowA(cur, slot)[k]; }
+    DEV int srcB(int k, int slot) const { return rowB(cur, slot)[k]; }
+    DEV void setA(int k, int slot) const { rowA(cur, slot)[k] = (uint8_t)slot; }
+    DEV void setB(int k, int slot) const { rowB(cur, slot)[k] = (uint8_t)slot; }
+    DEV typename Dom<T>::M* pm() const { return (typename Dom<T>::M*)(lds + pm_off); }
+    DEV typename Dom<T>::M* cpm() const { return (typename Dom<T>::M*)(lds + cpm_off); }
+    DEV uint64_t* ckey() const { return (uint64_t*)(lds + ckey_off); }
+    DEV uint16_t* surv() const { return (uint16_t*)(lds + surv_off); }
+    DEV uint16_t* sinfo() const { return (uint16_t*)(lds + sinfo_off); }
+    // LLR stage buffer: space SP, stage offset off (units), node size 2^k.
+    template <int SP>
+    DEV T* stage(int off, int k, int slot) const {
+        if constexpr (SP == SP_WS) return (T*)(wsb + (off << 8)) + (slot << k);
+        else return (T*)(lds + (off << 4)) + (slot << k);
     }
-    DEV uint8_t* rowB(int fi, int buf, int slot) const {
-        return fl(fi) + ptrB_off + ((buf * L + slot) << 4);
-    }
-    DEV int srcA(int fi, int k, int slot) const { return rowA(fi, cur, slot)[k]; }
-    DEV int srcB(int fi, int k, int slot) const { return rowB(fi, cur, slot)[k]; }
-    DEV void setA(int fi, int k, int slot) const { rowA(fi, cur, slot)[k] = (uint8_t)slot; }
-    DEV void setB(int fi, int k, int slot) const { rowB(fi, cur, slot)[k] = (uint8_t)slot; }
-    DEV typename Dom<T>::M* pm(int fi) const { return (typename Dom<T>::M*)(fl(fi) + pm_off); }
-    DEV unsigned char* scr(int fi) const { return fl(fi) + fb * scr_stride; }
-    DEV typename Dom<T>::M* cpm(int fi) const { return (typename Dom<T>::M*)(scr(fi) + cpm_off); }
-    DEV uint64_t* ckey(int fi) const { return (uint64_t*)(scr(fi) + ckey_off); }
-    DEV uint16_t* surv(int fi) const { return (uint16_t*)(scr(fi) + surv_off); }
-    DEV uint16_t* sinfo(int fi) const { return (uint16_t*)(scr(fi) + sinfo_off); }
-    DEV uint32_t* hdw(int fi) const { return (uint32_t*)(scr(fi) + hd_off); }
-    // partial-sum words of a slot at level k, stage base offset off
-    DEV uint32_t* bw(int fi, int off, int k, int slot) const {
-        if (off & 0x8000)
-            return (uint32_t*)(wsb + fi * ws_frame + ((off & 0x7fff) << 8)) + slot * words_of(k);
-        return (uint32_t*)(fl(fi) + (off << 4)) + slot * words_of(k);
-    }
-    DEV const T* chan(int fi) const {
-        int64_t f = f0 + fi;
-        if (f >= F) f = F - 1;
-        return llr + f * N;
+    // Partial-sum words of a slot at level k.
+    template <int SP>
+    DEV uint32_t* bw(int off, int k, int slot) const {
+        if constexpr (SP == SP_WS) return (uint32_t*)(wsb + (off << 8)) + slot * words_of(k);
+        else return (uint32_t*)(lds + (off << 4)) + slot * words_of(k);
     }
     template <int SP>
-    DEV T* stage(int fi, int off, int k, int slot) const {
-        if constexpr (SP == SP_WS) return (T*)(wsb + fi * ws_frame + (off << 8)) + (slot << k);
-        else return (T*)(fl(fi) + (off << 4)) + (slot << k);
-    }
-    // Leaf input through a generic pointer (workspace or channel row).
-    DEV const T* leaf_gen(int fi, int off, int k, int slot, int sp) const {
-        if (sp == SP_CH) return chan(fi);
-        return (const T*)(wsb + fi * ws_frame + (off << 8)) + (slot << k);
+    DEV const T* in_stage(int off, int k, int slot) const {
+        if constexpr (SP == SP_CH) return chan;
+        else return stage<SP>(off, k, slot);
     }
 };
 
 // ---------------------------------------------------------------------------
 // Lane groups.  Between two forking leaves every operation acts on each path
-// on its own (F, G, Combine, Rate-0), so each path instance (frame, path) is
-// given to a group of G lanes inside one wavefront and the whole run of
-// operations proceeds without workgroup barriers: LDS operations of one
-// wavefront complete in issue order, and a wavefront-level fence keeps the
-// compiler from reordering them.
+// on its own (F, G, Combine, Rate-0), so each path is given to a group of G
+// lanes inside one wavefront and the whole run of operations proceeds
+// without workgroup barriers: memory operations of one wavefront complete in
+// issue order, and a wavefront-level fence keeps the compiler from reordering
+// them.
 // ---------------------------------------------------------------------------
 
 struct Grp {
-    int fi, p, g, G;
+    int p, g, G;
     bool valid;
 };
 
-DEV Grp make_grp(int tid, int NT, int FW, int P) {
-    const int I = FW * P;
+DEV Grp make_grp(int tid, int NT, int P) {
     const int NW = NT >> 6;
-    int ipw = (I + NW - 1) / NW;
+    int ipw = (P + NW - 1) / NW;  // paths per wavefront
     ipw = ipw <= 1 ? 1 : (1 << (32 - __clz(ipw - 1)));
-    if (ipw > 64) ipw = 64;
     Grp q;
     q.G = 64 / ipw;
     const int lg = ilog2u(q.G);
     const int lane = tid & 63;
     const int inst = (tid >> 6) * ipw + (lane >> lg);
-    q.valid = inst < I;
-    const int lP = ilog2u(P);
-    q.fi = q.valid ? (inst >> lP) : 0;
-    q.p = q.valid ? (inst & (P - 1)) : 0;
+    q.valid = inst < P;
+    q.p = q.valid ? inst : 0;
     q.g = lane & (q.G - 1);
     return q;
 }
@@ -313,7 +298,7 @@ DEV void wave_sync() {
 
 // F / G of one path at a level-k node, eqs. (f) and (g): lane g of the group
 // takes 16-byte chunks g, g + G, ..., up to U of them loaded before any is
-// stored.
+// stored.  The left partial sums of G share the output's space.
 template <typename T, bool IS_G, int ISP, int OSP>
 DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     using IO = VecIO<T>;
@@ -324,12 +309,10 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     constexpr int U = 4;
     if (!q.valid) return;
     const int M = 1 << (k - 1);
-    const T* in;
-    if constexpr (ISP == SP_CH) in = c.chan(q.fi);
-    else in = c.template stage<ISP>(q.fi, op.x, k, c.srcA(q.fi, k, q.p));
-    T* out = c.template stage<OSP>(q.fi, op.y, k - 1, q.p);
+    const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, q.p));
+    T* out = c.template stage<OSP>(op.y, k - 1, q.p);
     const uint32_t* bl = nullptr;
-    if constexpr (IS_G) bl = c.bw(q.fi, op.z, k - 1, c.srcB(q.fi, k - 1, q.p));
+    if constexpr (IS_G) bl = c.template bw<OSP>(op.z, k - 1, c.srcB(k - 1, q.p));
     if (M >= V) {
         const int nch = M >> LOGV;
         for (int ch0 = q.g; ch0 < nch; ch0 += q.G * U) {
@@ -371,7 +354,7 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
             out[i] = (T)v;
         }
     }
-    if (q.g == 0) c.setA(q.fi, k - 1, q.p);
+    if (q.g == 0) c.setA(k - 1, q.p);
 }
 
 template <typename T, bool IS_G>
@@ -389,13 +372,13 @@ DEV void pp_fg_any(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
 }
 
 // Combine, eq. (combine), on bit-packed words: beta_v = (beta_l ^ beta_r, beta_r).
-template <typename T>
+template <typename T, int ISP, int OSP>
 DEV void pp_comb(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
     if (!q.valid) return;
     const int W = words_of(k);
-    const uint32_t* l = c.bw(q.fi, op.x, k - 1, c.srcB(q.fi, k - 1, q.p));
-    const uint32_t* r = c.bw(q.fi, op.y, k - 1, q.p);
-    uint32_t* o = c.bw(q.fi, op.z, k, q.p);
+    const uint32_t* l = c.template bw<ISP>(op.x, k - 1, c.srcB(k - 1, q.p));
+    const uint32_t* r = c.template bw<ISP>(op.y, k - 1, q.p);
+    uint32_t* o = c.template bw<OSP>(op.z, k, q.p);
     if (k >= 6) {
         const int hw = W >> 1;
         for (int w = q.g; w < hw; w += q.G) {
@@ -409,7 +392,15 @@ DEV void pp_comb(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q
         const uint32_t lv = l[0] & m, rv = r[0] & m;
         o[0] = (lv ^ rv) | (rv << h);
     }
-    if (side == 0 && q.g == 0) c.setB(q.fi, k, q.p);
+    if (side == 0 && q.g == 0) c.setB(k, q.p);
+}
+
+template <typename T>
+DEV void pp_comb_any(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
+    const int isp = op_isp(op), osp = op_osp(op);
+    if (isp == SP_LDS && osp == SP_LDS) pp_comb<T, SP_LDS, SP_LDS>(c, op, k, side, q);
+    else if (isp == SP_LDS) pp_comb<T, SP_LDS, SP_WS>(c, op, k, side, q);
+    else pp_comb<T, SP_WS, SP_WS>(c, op, k, side, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -484,12 +475,12 @@ DEV void leaf_scan(const T* in, int nv, int g, int G, Fn fn) {
             IO::unpack(q0, v);
 #pragma unroll
             for (int j = 0; j < IO::V; ++j)
-                fn((ch << IO::LOGV) + j, (ISP == SP_LDS) ? v[j] : D::load(v[j]));
+                fn((ch << IO::LOGV) + j, (ISP == SP_CH) ? D::load(v[j]) : v[j]);
             if (ch2 < nch) {
                 IO::unpack(q1, v);
 #pragma unroll
                 for (int j = 0; j < IO::V; ++j)
-                    fn((ch2 << IO::LOGV) + j, (ISP == SP_LDS) ? v[j] : D::load(v[j]));
+                    fn((ch2 << IO::LOGV) + j, (ISP == SP_CH) ? D::load(v[j]) : v[j]);
             }
         }
     } else {
@@ -497,16 +488,10 @@ DEV void leaf_scan(const T* in, int nv, int g, int G, Fn fn) {
     }
 }
 
-template <typename T, int ISP>
-DEV const T* leaf_input(const Ctx<T>& c, const OpRec& op, int fi, int k, int slot) {
-    if constexpr (ISP == SP_LDS) return c.template stage<SP_LDS>(fi, op.x, k, slot);
-    else return c.leaf_gen(fi, op.x, k, slot, op_isp(op));
-}
-
 // Hard decisions (eq. (info)) of elements 32w .. 32w + 31 of a leaf input
 // as one word (bit x = element 32w + x; nodes shorter than 32 use the low
 // bits).
-template <typename T, int ISP>
+template <typename T>
 DEV uint32_t hd_word(const T* in, int w, int nv) {
     using IO = VecIO<T>;
     using D = Dom<T>;
@@ -538,13 +523,13 @@ DEV uint32_t hd_word(const T* in, int w, int nv) {
 
 // Rate-0 of one path, Sec. III-B: the metric loses the distance of the
 // all-zero word (eq. (rel:frozen-h)); the output is all zeros.
-template <typename T, int ISP>
+template <typename T, int ISP, int OSP>
 DEV void pp_rate0(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
     using D = Dom<T>;
     using A = typename D::A;
     using S = typename D::S;
     const int nv = 1 << k;
-    const T* in = leaf_input<T, ISP>(c, op, q.fi, k, c.srcA(q.fi, k, q.p));
+    const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, q.p));
     S s = 0;
     if (q.valid) {
         leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int, A v) {
@@ -553,10 +538,10 @@ DEV void pp_rate0(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& 
     }
     for (int m = 1; m < q.G; m <<= 1) s += shfl_xor_s<S>(s, m);
     if (!q.valid) return;
-    if (q.g == 0) c.pm(q.fi)[q.p] = D::sub(c.pm(q.fi)[q.p], D::round_pen(s));
-    uint32_t* o = c.bw(q.fi, op.y, k, q.p);
+    if (q.g == 0) c.pm()[q.p] = D::sub(c.pm()[q.p], D::round_pen(s));
+    uint32_t* o = c.template bw<OSP>(op.y, k, q.p);
     for (int w = q.g; w < words_of(k); w += q.G) o[w] = 0u;
-    if (side == 0 && q.g == 0) c.setB(q.fi, k, q.p);
+    if (side == 0 && q.g == 0) c.setB(k, q.p);
 }
 
 // Pass 1 of a forking leaf for one source path: its statistics and the
@@ -570,19 +555,11 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
     const int nv = 1 << k;
     const int lc = ilog2u(ccount);
     const int s = q.p;
-    const T* in = leaf_input<T, ISP>(c, op, q.fi, k, c.srcA(q.fi, k, s));
-    M* cp = c.cpm(q.fi) + (s << lc);
-    uint64_t* ck = c.ckey(q.fi) + (s << lc);
-    uint16_t* si = c.sinfo(q.fi) + s * 8;
-    const M pms = c.pm(q.fi)[s];
-    // The source's hard decisions are saved for pass 3: by then another
-    // path may already be writing this LLR stage buffer.
-    if ((TYPE == OP_R1 && k > 0) || TYPE == OP_SPC) {
-        if (q.valid) {
-            uint32_t* hd = c.hdw(q.fi) + s * c.hd_words;
-            for (int w = q.g; w < words_of(k); w += q.G) hd[w] = hd_word<T, ISP>(in, w, nv);
-        }
-    }
+    const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, s));
+    M* cp = c.cpm() + (s << lc);
+    uint64_t* ck = c.ckey() + (s << lc);
+    uint16_t* si = c.sinfo() + s * 8;
+    const M pms = c.pm()[s];
     auto put = [&](int r, M v) {
         cp[r] = v;
         ck[r] = ((uint64_t)D::order(v) << 32) | (uint32_t)(0xffff - ((s << lc) + r));
@@ -704,34 +681,43 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
 
 template <typename T, int TYPE>
 DEV void pp_fork_score_any(const Ctx<T>& c, const OpRec& op, int k, int cc, const Grp& q) {
-    if (op_isp(op) == SP_LDS) pp_fork_score<T, TYPE, SP_LDS>(c, op, k, cc, q);
-    else pp_fork_score<T, TYPE, SP_WS>(c, op, k, cc, q);
+    const int isp = op_isp(op);
+    if (isp == SP_LDS) pp_fork_score<T, TYPE, SP_LDS>(c, op, k, cc, q);
+    else if (isp == SP_WS) pp_fork_score<T, TYPE, SP_WS>(c, op, k, cc, q);
+    else pp_fork_score<T, TYPE, SP_CH>(c, op, k, cc, q);
+}
+
+template <typename T>
+DEV void pp_rate0_any(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& q) {
+    const int isp = op_isp(op), osp = op_osp(op);
+    if (isp == SP_LDS) pp_rate0<T, SP_LDS, SP_LDS>(c, op, k, side, q);
+    else if (isp == SP_WS) pp_rate0<T, SP_WS, SP_WS>(c, op, k, side, q);
+    else if (osp == SP_LDS) pp_rate0<T, SP_CH, SP_LDS>(c, op, k, side, q);
+    else pp_rate0<T, SP_CH, SP_WS>(c, op, k, side, q);
 }
 
 // Candidate selection, Alg. 1, over the whole workgroup: a candidate's rank
-// is the number of candidates of its frame that beat it (larger metric, or
-// equal metric and smaller enumeration index), counted by TP lanes over
-// disjoint slices and summed; ranks 0..L-1 survive, best first.
+// is the number of candidates that beat it (larger metric, or equal metric
+// and smaller enumeration index), counted by TP lanes over disjoint slices
+// and summed; ranks 0..L-1 survive, best first.
 template <typename T>
 DEV void select_rank(const Ctx<T>& c, int C, int L) {
     const int lC = ilog2u(C);
-    int TP = c.NT / (c.FW << lC);
+    int TP = c.NT >> lC;
     TP = TP < 1 ? 1 : (TP > 64 ? 64 : TP);
-    TP = 1 << ilog2u(TP);
     if (C >= 8 && TP > (C >> 3)) TP = C >> 3;  // slices of at least 8 keys
     if (C < 8) TP = 1;
     const int lt = ilog2u(TP);
     const int span = C >> lt;
-    const int total = c.FW << (lC + lt);
+    const int total = 1 << (lC + lt);
     const int wave = c.tid >> 6;
+    const uint64_t* ck = c.ckey();
     for (int base = wave * 64; base < total; base += c.NT) {
         const int it = base + c.lane;
         const bool act = it < total;
         const int itc = act ? it : total - 1;
-        const int fi = itc >> (lC + lt);
-        const int e = (itc >> lt) & (C - 1);
+        const int e = itc >> lt;
         const int t = itc & (TP - 1);
-        const uint64_t* ck = c.ckey(fi);
         const uint64_t mine = ck[e];
         const int e0 = t * span;
         int rank = 0;
@@ -751,34 +737,34 @@ DEV void select_rank(const Ctx<T>& c, int C, int L) {
             for (int e2 = e0; e2 < e0 + span; ++e2) rank += ck[e2] > mine ? 1 : 0;
         }
         for (int m = 1; m < TP; m <<= 1) rank += shfl_xor_i(rank, m);
-        if (act && t == 0 && rank < L) c.surv(fi)[rank] = (uint16_t)e;
+        if (act && t == 0 && rank < L) c.surv()[rank] = (uint16_t)e;
     }
 }
 
 // Pass 3 of a forking leaf for one destination slot j: its metric, its path
 // tables (a copy of its source's, sharing every stage buffer), and its
-// codeword (the source's hard decisions with the candidate's flips).
-template <typename T, int TYPE>
-DEV void pp_fork_emit(Ctx<T>& c, int k, int side, int ccount, bool prune, int b_out,
+// codeword (the source's saved hard decisions with the candidate's flips).
+template <typename T, int TYPE, int ISP, int OSP>
+DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, bool prune,
                       const Grp& q) {
     if (!q.valid) return;
     const int nv = 1 << k;
     const int lc = ilog2u(ccount);
     const int j = q.p;
-    const int e = prune ? c.surv(q.fi)[j] : j;
+    const int e = prune ? c.surv()[j] : j;
     const int s = e >> lc;
     const int r = e & (ccount - 1);
-    const uint16_t* si = c.sinfo(q.fi) + s * 8;
+    const uint16_t* si = c.sinfo() + s * 8;
     const int W = words_of(k);
     const uint32_t full = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
-    const uint32_t* hd = c.hdw(q.fi) + s * c.hd_words;
-    uint32_t* o = c.bw(q.fi, b_out, k, j);
+    const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, s));
+    uint32_t* o = c.template bw<OSP>(op.y, k, j);
     for (int w = q.g; w < W; w += q.G) {
         uint32_t word;
         if (TYPE == OP_REP || (TYPE == OP_R1 && k == 0)) {
             word = ((si[4] ^ r) & 1) ? full : 0u;
         } else {
-            word = hd[w];
+            word = hd_word<T>(in, w, nv);
             uint32_t dm;
             if constexpr (TYPE == OP_R1) dm = (uint32_t)r;
             else dm = spc_flips(r) ^ (si[4] ? 1u : 0u);
@@ -792,52 +778,58 @@ DEV void pp_fork_emit(Ctx<T>& c, int k, int side, int ccount, bool prune, int b_
     }
     if (q.g == 0) {
         const int nxt = c.cur ^ 1;
-        *(uint4*)c.rowA(q.fi, nxt, j) = *(const uint4*)c.rowA(q.fi, c.cur, s);
-        *(uint4*)c.rowB(q.fi, nxt, j) = *(const uint4*)c.rowB(q.fi, c.cur, s);
-        if (side == 0) c.rowB(q.fi, nxt, j)[k] = (uint8_t)j;
-        c.pm(q.fi)[j] = c.cpm(q.fi)[e];
+        *(uint4*)c.rowA(nxt, j) = *(const uint4*)c.rowA(c.cur, s);
+        *(uint4*)c.rowB(nxt, j) = *(const uint4*)c.rowB(c.cur, s);
+        if (side == 0) c.rowB(nxt, j)[k] = (uint8_t)j;
+        c.pm()[j] = c.cpm()[e];
     }
 }
 
 // Pass 3 of the pending fork described by op.
+template <typename T, int TYPE>
+DEV void pp_emit_typed(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
+    const int k = op_k(op), side = op_side(op), cc = op_cand(op);
+    const int isp = op_isp(op), osp = op_osp(op);
+    if (isp == SP_LDS) pp_fork_emit<T, TYPE, SP_LDS, SP_LDS>(c, op, k, side, cc, prune, q);
+    else if (isp == SP_WS) pp_fork_emit<T, TYPE, SP_WS, SP_WS>(c, op, k, side, cc, prune, q);
+    else if (osp == SP_LDS) pp_fork_emit<T, TYPE, SP_CH, SP_LDS>(c, op, k, side, cc, prune, q);
+    else pp_fork_emit<T, TYPE, SP_CH, SP_WS>(c, op, k, side, cc, prune, q);
+}
+
 template <typename T>
 DEV void pp_emit_pending(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
     const int type = op_type(op);
-    const int k = op_k(op), side = op_side(op);
-    const int cc = op_cand(op);
-    if (type == OP_REP) pp_fork_emit<T, OP_REP>(c, k, side, cc, prune, op.y, q);
-    else if (type == OP_R1) pp_fork_emit<T, OP_R1>(c, k, side, cc, prune, op.y, q);
-    else pp_fork_emit<T, OP_SPC>(c, k, side, cc, prune, op.y, q);
+    if (type == OP_REP) pp_emit_typed<T, OP_REP>(c, op, prune, q);
+    else if (type == OP_R1) pp_emit_typed<T, OP_R1>(c, op, prune, q);
+    else pp_emit_typed<T, OP_SPC>(c, op, prune, q);
     c.cur ^= 1;  // path tables now in the other buffer
-    c.fb ^= 1;   // the next fork uses the other candidate scratch
 }
 
 // ---------------------------------------------------------------------------
 // Final choice: CRC syndromes, best passing path, u = x G_N, output.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t* crc_ok,
-                void* pm_out) {
+template <typename T, int RSP>
+DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_hat,
+                uint8_t* crc_ok, void* pm_out) {
     using D = Dom<T>;
     const int n = c.n;
     const int W = words_of(n);
     const int lP = ilog2u(P);
     const int wave = c.tid >> 6;
-    // syndromes: one group of lanes per (frame, path)
+    // syndromes: one group of lanes per path
     {
         const int G = W < 64 ? W : 64;
         const int lg = ilog2u(G);
         const int cnt = W >> lg;
-        const int total = c.FW << (lP + lg);
+        const int total = 1 << (lP + lg);
         for (int base = wave * 64; base < total; base += c.NT) {
             const int it = base + c.lane;
             const bool act = it < total;
             const int itc = act ? it : total - 1;
-            const int fi = itc >> (lP + lg);
-            const int j = (itc >> lg) & (P - 1);
+            const int j = itc >> lg;
             const int g = itc & (G - 1);
-            const uint32_t* x = c.bw(fi, c.root_off, n, j);
+            const uint32_t* x = c.template bw<RSP>(a.root_off, n, j);
             uint64_t acc = 0;
             if (a.has_crc) {
                 const int nb = c.N < 32 ? c.N : 32;
@@ -853,75 +845,50 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
                 }
                 for (int m = 1; m < G; m <<= 1) acc ^= shfl_xor64(acc, m);
             }
-            if (act && g == 0) c.surv(fi)[j] = (acc == 0) ? 1 : 0;
+            if (act && g == 0) c.surv()[j] = (acc == 0) ? 1 : 0;
         }
     }
     __syncthreads();
-    // pick: one lane per (frame, path), segments of P lanes
-    {
-        const int total = c.FW << lP;
-        for (int base = wave * 64; base < total; base += c.NT) {
-            const int it = base + c.lane;
-            const bool act = it < total;
-            const int itc = act ? it : total - 1;
-            const int fi = itc >> lP;
-            const int j = itc & (P - 1);
-            const uint64_t pass = c.surv(fi)[j] & 1;
-            uint64_t key = (pass << 40) | ((uint64_t)D::order(c.pm(fi)[j]) << 8) | (uint64_t)(255 - j);
-            for (int m = 1; m < P; m <<= 1) key = umax64(key, shfl_xor64(key, m));
-            if (act && j == 0) {
-                const int best = 255 - (int)(key & 0xff);
-                const int ok = (int)(key >> 40) & 1;
-                c.sinfo(fi)[0] = (uint16_t)best;
-                const int64_t f = c.f0 + fi;
-                if (f < c.F) {
-                    if (crc_ok) crc_ok[f] = (uint8_t)ok;
-                    if (pm_out) ((uint32_t*)pm_out)[f] = D::bits(c.pm(fi)[best]);
-                }
-            }
+    // pick: one lane per path
+    if (c.tid < 64) {
+        const int j = c.lane < P ? c.lane : 0;
+        const uint64_t pass = c.surv()[j] & 1;
+        uint64_t key = (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+        for (int m = 1; m < P; m <<= 1) key = umax64(key, shfl_xor64(key, m));
+        if (c.lane == 0) {
+            const int best = 255 - (int)(key & 0xff);
+            const int ok = (int)(key >> 40) & 1;
+            c.sinfo()[0] = (uint16_t)best;
+            if (crc_ok) crc_ok[f] = (uint8_t)ok;
+            if (pm_out) ((uint32_t*)pm_out)[f] = D::bits(c.pm()[best]);
         }
     }
     __syncthreads();
     // u = x G_N on the chosen codeword, in place: bits within words ...
-    {
-        const int lw = ilog2u(W);
-        const int total = c.FW << lw;
-        for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it >> lw;
-            const int w = it & (W - 1);
-            uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
-            uint32_t v = x[w];
-            v ^= (v >> 1) & 0x55555555u;
-            v ^= (v >> 2) & 0x33333333u;
-            v ^= (v >> 4) & 0x0f0f0f0fu;
-            v ^= (v >> 8) & 0x00ff00ffu;
-            v ^= (v >> 16) & 0x0000ffffu;
-            x[w] = v;
-        }
+    for (int w = c.tid; w < W; w += c.NT) {
+        uint32_t* x = c.template bw<RSP>(a.root_off, n, c.sinfo()[0]);
+        uint32_t v = x[w];
+        v ^= (v >> 1) & 0x55555555u;
+        v ^= (v >> 2) & 0x33333333u;
+        v ^= (v >> 4) & 0x0f0f0f0fu;
+        v ^= (v >> 8) & 0x00ff00ffu;
+        v ^= (v >> 16) & 0x0000ffffu;
+        x[w] = v;
     }
     // ... then across words
     for (int sw = 1; sw < W; sw <<= 1) {
         __syncthreads();
-        const int lw = ilog2u(W);
-        const int total = c.FW << lw;
-        for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it >> lw;
-            const int w = it & (W - 1);
+        for (int w = c.tid; w < W; w += c.NT) {
             if (w & sw) continue;
-            uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
+            uint32_t* x = c.template bw<RSP>(a.root_off, n, c.sinfo()[0]);
             x[w] ^= x[w + sw];
         }
     }
     __syncthreads();
     {
+        const uint32_t* x = c.template bw<RSP>(a.root_off, n, c.sinfo()[0]);
         const int K = a.K;
-        const int total = c.FW * K;
-        for (int it = c.tid; it < total; it += c.NT) {
-            const int fi = it / K;
-            const int t = it - fi * K;
-            const int64_t f = c.f0 + fi;
-            if (f >= c.F) continue;
-            const uint32_t* x = c.bw(fi, c.root_off, n, c.sinfo(fi)[0]);
+        for (int t = c.tid; t < K; t += c.NT) {
             const int p = a.info_pos[t];
             u_hat[f * K + t] = (uint8_t)((x[p >> 5] >> (p & 31)) & 1u);
         }
@@ -929,80 +896,65 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, uint8_t* u_hat, uint8_t*
 }
 
 // ---------------------------------------------------------------------------
-// The kernel: a persistent grid; each workgroup takes FW frames at a time.
+// The kernel: a persistent grid; each workgroup decodes one frame at a time.
 // ---------------------------------------------------------------------------
 
 template <typename T>
 __global__ void __launch_bounds__(1024)
-    decode_kernel(KArgs a, const T* __restrict__ llr, int64_t F, uint8_t* __restrict__ u_hat,
-                  uint8_t* __restrict__ crc_ok, void* __restrict__ pm_out) {
+    decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
+                  uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
+                  void* __restrict__ pm_out) {
     extern __shared__ __align__(16) unsigned char lds[];
     Ctx<T> c;
     c.lds = lds;
-    c.wsb = a.ws + (int64_t)blockIdx.x * a.FW * a.ws_frame;
-    c.llr = llr;
-    c.F = F;
-    c.ws_frame = a.ws_frame;
-    c.lds_frame = a.lds_frame;
+    c.wsb = a.ws + (int64_t)blockIdx.x * a.ws_frame;
     c.N = a.N;
     c.n = a.n;
     c.L = a.L;
-    c.FW = a.FW;
     c.tid = threadIdx.x;
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
     c.ptrA_off = a.ptrA_off;
     c.ptrB_off = a.ptrB_off;
     c.pm_off = a.pm_off;
-    c.root_off = a.root_off;
     c.cpm_off = a.cpm_off;
     c.ckey_off = a.ckey_off;
     c.surv_off = a.surv_off;
     c.sinfo_off = a.sinfo_off;
-    c.hd_off = a.hd_off;
-    c.hd_words = a.hd_words;
-    c.scr_stride = a.scr_stride;
-    c.fb = 0;
 
-    // The schedule is read from LDS: one broadcast read per operation,
-    // issued while the previous operation runs.
-    // (Schedules too long for LDS are read from global memory instead.)
-    const OpRec* sched = a.ops;
-    if (a.sched_lds) {
-        OpRec* s = (OpRec*)(lds + a.FW * a.lds_frame);
-        for (int i = c.tid; i < a.n_ops; i += c.NT) s[i] = a.ops[i];
-        sched = s;
-    }
-    __syncthreads();
+    // Schedule records are read with scalar loads (the schedule is a
+    // read-only argument), the next one while the current operation runs.
 
-    for (int64_t f0 = (int64_t)blockIdx.x * a.FW; f0 < F; f0 += (int64_t)gridDim.x * a.FW) {
-        c.f0 = f0;
+    for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
+        c.chan = llr + f * a.N;
         c.cur = 0;
-        for (int fi = c.tid; fi < c.FW; fi += c.NT) c.pm(fi)[0] = 0;
+        if (c.tid == 0) c.pm()[0] = 0;
         __syncthreads();
         int P = 1;
-        Grp q = make_grp(c.tid, c.NT, c.FW, P);
-        c.fb = 0;
+        Grp q = make_grp(c.tid, c.NT, P);
         // a fork whose survivors still have to be written (pass 3)
         int pend = 0;
         OpRec pop{};
         int pprune = 0;
-        OpRec nop = sched[0];
+        uint64_t nraw = sched[0];
         for (int oi = 0; oi < a.n_ops; ++oi) {
+            const uint64_t raw = nraw;
+            nraw = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
             OpRec op;
-            op.meta = (uint16_t)__builtin_amdgcn_readfirstlane(nop.meta);
-            op.x = (uint16_t)__builtin_amdgcn_readfirstlane(nop.x);
-            op.y = (uint16_t)__builtin_amdgcn_readfirstlane(nop.y);
-            op.z = (uint16_t)__builtin_amdgcn_readfirstlane(nop.z);
-            nop = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
+            op.meta = (uint16_t)raw;
+            op.x = (uint16_t)(raw >> 16);
+            op.y = (uint16_t)(raw >> 32);
+            op.z = (uint16_t)(raw >> 48);
             const int type = op_type(op);
             const int k = op_k(op);
             const int side = op_side(op);
             const int cc = op_cand(op);
             if (pend) {
+                // every survivor is written before any path's next operation
+                // overwrites a stage buffer or the candidate scratch
                 pp_emit_pending<T>(c, pop, pprune, q);
                 pend = 0;
-                wave_sync();
+                __syncthreads();
             }
             switch (type) {
                 case OP_F:
@@ -1012,11 +964,10 @@ __global__ void __launch_bounds__(1024)
                     pp_fg_any<T, true>(c, op, k, q);
                     break;
                 case OP_COMB:
-                    pp_comb<T>(c, op, k, side, q);
+                    pp_comb_any<T>(c, op, k, side, q);
                     break;
                 case OP_R0:
-                    if (op_isp(op) == SP_LDS) pp_rate0<T, SP_LDS>(c, op, k, side, q);
-                    else pp_rate0<T, SP_WS>(c, op, k, side, q);
+                    pp_rate0_any<T>(c, op, k, side, q);
                     break;
                 default: {
                     // a forking leaf: score, select across the workgroup, and
@@ -1032,7 +983,7 @@ __global__ void __launch_bounds__(1024)
                         __syncthreads();
                     }
                     P = pprune ? c.L : C;
-                    q = make_grp(c.tid, c.NT, c.FW, P);
+                    q = make_grp(c.tid, c.NT, P);
                     pend = 1;
                     pop = op;
                     break;
@@ -1042,7 +993,8 @@ __global__ void __launch_bounds__(1024)
         }
         if (pend) pp_emit_pending<T>(c, pop, pprune, q);
         __syncthreads();
-        finish<T>(c, a, P, u_hat, crc_ok, pm_out);
+        if (a.root_sp == SP_LDS) finish<T, SP_LDS>(c, a, P, f, u_hat, crc_ok, pm_out);
+        else finish<T, SP_WS>(c, a, P, f, u_hat, crc_ok, pm_out);
         __syncthreads();
     }
 }
@@ -1069,7 +1021,7 @@ struct pscl_plan {
     uint16_t* d_info = nullptr;
     uint8_t* d_ws = nullptr;
     KArgs args{};
-    int NT = 256, FW = 1, grid_max = 0, lds_bytes = 0, k_glob = 0;
+    int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int64_t ws_bytes = 0;
     const void* kernel = nullptr;
 };
@@ -1095,11 +1047,13 @@ const void* kernel_for(int dtype) {
     }
 }
 
-// Per-frame layout for a given first global stage.  LLR stages below k_glob
-// and all partial sums, path tables and candidate scratch live in LDS; LLR
-// stages k_glob..n-1 live in the workspace.  Returns the LDS bytes per frame.
+// Per-frame layout for a given first global level k_glob: LLR stages and
+// partial-sum levels below k_glob live in LDS, the others in the global
+// workspace; path tables, metrics and candidate scratch always in LDS.
+// Offsets are recorded in 16-byte (LDS) or 256-byte (workspace) units.
+// Returns the LDS bytes.
 struct Layout {
-    int a_off[MAXLVL];  // LLR stage offsets (LDS or workspace)
+    int a_off[MAXLVL];  // LLR stages
     int bl_off[MAXLVL], br_off[MAXLVL];
     int64_t ws_frame;
 };
@@ -1108,33 +1062,22 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     const int L = p->L, n = p->n, es = elem_size(p->dtype);
     int off = 0;
     int64_t woff = 0;
-    for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
-    for (int k = 0; k < n; ++k) {
-        const int bytes = L * (1 << k) * es;
-        if (k < k_glob) {
-            lay.a_off[k] = off;
+    auto place = [&](int bytes, bool lds) {
+        if (lds) {
+            const int v = off >> 4;
             off = align16(off + bytes);
-        } else {
-            lay.a_off[k] = (int32_t)woff;
-            woff += (bytes + 255) & ~255;
+            return v;
         }
-    }
-    // partial sums of level k sit in LDS when k < k_glob, else in the
-    // workspace (offset flagged with bit 15)
+        const int v = (int)(woff >> 8);
+        woff += (bytes + 255) & ~255;
+        return v;
+    };
+    for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
+    for (int k = 0; k < n; ++k) lay.a_off[k] = place(L * (1 << k) * es, k < k_glob);
     for (int k = 0; k <= n; ++k) {
         const int bytes = L * words_host(k) * 4;
-        for (int side = 0; side < 2; ++side) {
-            if (side == 0 && k == n) continue;  // the root is never a left child
-            int val;
-            if (k < k_glob) {
-                val = off >> 4;
-                off = align16(off + bytes);
-            } else {
-                val = 0x8000 | (int)(woff >> 8);
-                woff += (bytes + 255) & ~255;
-            }
-            (side == 0 ? lay.bl_off : lay.br_off)[k] = val;
-        }
+        if (k < n) lay.bl_off[k] = place(bytes, k < k_glob);  // the root is never a left child
+        lay.br_off[k] = place(bytes, k < k_glob);
     }
     a.ptrA_off = off;
     off = align16(off + 2 * 16 * L);
@@ -1142,56 +1085,47 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     off = align16(off + 2 * 16 * L);
     a.pm_off = off;
     off = align16(off + 4 * L);
-    // candidate scratch (two copies, scr_stride apart): metrics and ranking
-    // keys of up to 8 candidates per path, survivors, per-source statistics
-    // and the sources' hard decisions
-    int hd_words = 1;
-    for (const SchedOp& s : p->sched)
-        if (s.type == OP_R1 || s.type == OP_SPC) hd_words = std::max(hd_words, words_host(s.k));
-    const int base = off;
-    int so = 0;
-    a.cpm_off = base + so;
-    so = align16(so + 4 * 8 * L);
-    a.ckey_off = base + so;
-    so = align16(so + 8 * 8 * L);
-    a.surv_off = base + so;
-    so = align16(so + 2 * 8 * L);
-    a.sinfo_off = base + so;
-    so = align16(so + 16 * L);
-    a.hd_off = base + so;
-    so = align16(so + 4 * hd_words * L);
-    a.hd_words = hd_words;
-    a.scr_stride = so;
-    off = base + 2 * so;
+    // candidate scratch: metrics and ranking keys of up to 8 candidates per
+    // path, survivors, per-source statistics
+    a.cpm_off = off;
+    off = align16(off + 4 * 8 * L);
+    a.ckey_off = off;
+    off = align16(off + 8 * 8 * L);
+    a.surv_off = off;
+    off = align16(off + 2 * 8 * L);
+    a.sinfo_off = off;
+    off = align16(off + 16 * L);
     a.root_off = lay.br_off[n];
+    a.root_sp = n < k_glob ? SP_LDS : SP_WS;
     lay.ws_frame = woff;
     return off;
 }
 
-// Operation records: the schedule with every operand offset resolved.
-// LLR stage offsets: LDS in 16-byte units, workspace in 256-byte units.
-static uint16_t unit_off(int off, bool ws) { return (uint16_t)(ws ? (off >> 8) : (off >> 4)); }
-
+// Operation records: the schedule with every operand offset and space.
 std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glob) {
     const int n = p->n;
-    auto space = [&](int k) { return k == n ? SP_CH : (k >= k_glob ? SP_WS : SP_LDS); };
+    auto lvl = [&](int k) { return k < k_glob ? SP_LDS : SP_WS; };
     std::vector<OpRec> out;
     for (const SchedOp& s : p->sched) {
         OpRec r{};
         const int k = s.k;
-        int isp = space(k), osp = SP_LDS;
+        int isp, osp;
         if (s.type == OP_F || s.type == OP_G) {
-            osp = (k - 1) >= k_glob ? SP_WS : SP_LDS;
-            r.x = k < n ? unit_off(lay.a_off[k], isp == SP_WS) : 0;
-            r.y = unit_off(lay.a_off[k - 1], osp == SP_WS);
+            isp = k == n ? SP_CH : lvl(k);
+            osp = lvl(k - 1);
+            r.x = (uint16_t)(k < n ? lay.a_off[k] : 0);
+            r.y = (uint16_t)lay.a_off[k - 1];
             r.z = (uint16_t)lay.bl_off[k - 1];
         } else if (s.type == OP_COMB) {
-            isp = SP_LDS;
+            isp = lvl(k - 1);
+            osp = lvl(k);
             r.x = (uint16_t)lay.bl_off[k - 1];
             r.y = (uint16_t)lay.br_off[k - 1];
             r.z = (uint16_t)(s.side ? lay.br_off[k] : lay.bl_off[k]);
         } else {
-            r.x = k < n ? unit_off(lay.a_off[k], isp == SP_WS) : 0;
+            isp = k == n ? SP_CH : lvl(k);
+            osp = lvl(k);
+            r.x = (uint16_t)(k < n ? lay.a_off[k] : 0);
             r.y = (uint16_t)(s.side ? lay.br_off[k] : lay.bl_off[k]);
         }
         r.meta = (uint16_t)((uint32_t)s.type | ((uint32_t)k << 3) | ((uint32_t)s.side << 7) |
@@ -1291,15 +1225,15 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     // allows; larger stages go to the global workspace.  The budget trades
     // LDS per frame (stages kept on chip) against frames resident per CU.
     const int lds_hw = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
-    int lds_cap = std::min(lds_hw, 20 * 1024);
+    // A small budget keeps many frames resident per CU (their dependent
+    // chains overlap); the top stages then live in the workspace.
+    int lds_cap = std::min(lds_hw, 12 * 1024);
     if (const char* e = getenv("PSCL_LDS_BUDGET")) lds_cap = std::max(4096, std::min(lds_hw, atoi(e)));
     Layout lay;
     KArgs a{};
     int k_glob = p->n + 1;
     int bytes = layout(p, k_glob, lay, a);
-    // The schedule goes to LDS when it is short (at most 16 KiB).
-    const int sched_all = align16((int)p->sched.size() * (int)sizeof(OpRec));
-    const int sched_need = sched_all <= 16384 ? sched_all : 0;
+    const int sched_need = 0;
     while (bytes + sched_need > lds_cap && k_glob > 0) {
         --k_glob;
         bytes = layout(p, k_glob, lay, a);
@@ -1319,19 +1253,11 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
         return PSCL_E_UNSUPPORTED;
     }
     const int64_t wsf = lay.ws_frame;
-    // Frames per workgroup: lockstep frames share each operation's barrier;
-    // fill up to a quarter of the LDS budget, at most 8.
-    const int sched_bytes = sched_need;
-    int FW = std::max(1, std::min(8, (lds_cap / 4) / bytes));
-    while (FW > 1 && bytes * FW + sched_bytes > lds_cap) --FW;
-    p->FW = FW;
-    p->lds_bytes = bytes * FW + sched_bytes;
-    // Threads: with one resident workgroup per CU use 1024 threads (16
-    // waves) so that memory latency overlaps across waves; otherwise fewer.
+    p->lds_bytes = bytes + sched_need;
     // Few waves per frame: every schedule operation costs each of them its
     // control overhead, and more resident frames per CU hide the latency of
     // each frame's dependent chain better than more waves per frame.
-    p->NT = 128;
+    p->NT = dtype == PSCL_F32 ? 128 : 64;
     if (const char* e = getenv("PSCL_THREADS")) {
         const int t = atoi(e);
         if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) p->NT = t;
@@ -1348,7 +1274,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, p->kernel, p->NT, p->lds_bytes);
     if (e != hipSuccess || occ < 1) occ = 1;
     p->grid_max = occ * prop.multiProcessorCount;
-    p->ws_bytes = wsf * FW * (int64_t)p->grid_max;
+    p->ws_bytes = wsf * (int64_t)p->grid_max;
 
     std::vector<OpRec> ops = make_records(p, lay, k_glob);
     std::vector<uint64_t> syn(N, 0);
@@ -1383,11 +1309,8 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     a.n = p->n;
     a.K = K;
     a.L = L;
-    a.FW = FW;
-    a.lds_frame = bytes;
     p->k_glob = k_glob;
     a.has_crc = crc_len > 0 ? 1 : 0;
-    a.sched_lds = sched_need > 0 ? 1 : 0;
     p->args = a;
     *out = p;
     return PSCL_OK;
@@ -1396,7 +1319,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
 pscl_status pscl_plan_info(const pscl_plan* p, int* frames_per_wg, int* threads, int* workgroups,
                            int* lds_bytes, int64_t* workspace_bytes, int* first_global_stage) {
     if (!p) return PSCL_E_INVALID;
-    if (frames_per_wg) *frames_per_wg = p->FW;
+    if (frames_per_wg) *frames_per_wg = 1;
     if (threads) *threads = p->NT;
     if (workgroups) *workgroups = p->grid_max;
     if (lds_bytes) *lds_bytes = p->lds_bytes;
@@ -1413,21 +1336,23 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     if (((uintptr_t)llr & 15u) != 0) return PSCL_E_INVALID;  // 16-byte vector loads
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return PSCL_E_HIP;
-    const int64_t groups = (F + p->FW - 1) / p->FW;
-    const int grid = (int)std::min<int64_t>(groups, p->grid_max);
+    const int grid = (int)std::min<int64_t>(F, p->grid_max);
     hipStream_t s = (hipStream_t)stream;
     switch (p->dtype) {
         case PSCL_F32:
             hipLaunchKernelGGL(decode_kernel<float>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const float*)llr, F, u_hat, crc_ok, pm);
+                               p->args, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat,
+                               crc_ok, pm);
             break;
         case PSCL_I16:
             hipLaunchKernelGGL(decode_kernel<int16_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const int16_t*)llr, F, u_hat, crc_ok, pm);
+                               p->args, (const uint64_t*)p->d_ops, (const int16_t*)llr, F, u_hat,
+                               crc_ok, pm);
             break;
         default:
             hipLaunchKernelGGL(decode_kernel<int8_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const int8_t*)llr, F, u_hat, crc_ok, pm);
+                               p->args, (const uint64_t*)p->d_ops, (const int8_t*)llr, F, u_hat,
+                               crc_ok, pm);
             break;
     }
     e = hipGetLastError();
