@@ -54,6 +54,43 @@ def work_per_frame(pk, code, L):
             "total": int(f + g + reads + cands)}
 
 
+def kernel_source_hash(texts=None):
+    """Hash of the decoder sources with comments and whitespace removed, so
+    that only code changes invalidate recorded counters."""
+    import hashlib
+    import re
+
+    if texts is None:
+        texts = []
+        for rel in ("paper_1505_01466_amd/csrc/decoder.hip", "paper_1505_01466_amd/csrc/schedule.cpp"):
+            with open(os.path.join(ROOT, rel)) as fh:
+                texts.append(fh.read())
+    h = hashlib.sha256()
+    for t in texts:
+        t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", "", t)
+        h.update(re.sub(r"\s+", "", t).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(dtype):
+    """HBM bytes per frame of the decode kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy kernel),
+    or None when that summary was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "decode_kernel_2048_1723_L32_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = f"hbm_bytes_per_frame_{dtype}"
+    return float(vals[key]) if key in vals else None
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -70,9 +107,23 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "i16", "i8"])
     ap.add_argument("--frames", type=int, default=65536, help="frames per step")
     ap.add_argument("--ebn0", type=float, default=4.0)
-    ap.add_argument("--cpu-sample", type=int, default=2048,
+    ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="frames the oracle decodes for the CPU baseline (0 = skip)")
+    ap.add_argument("--single", action="store_true", help="time only --dtype")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": x.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: frames are independent, so more GPUs would "
               "split the batch with no exchange; --gpus above 1 is not supported.",
@@ -88,46 +139,65 @@ def main():
     torch.cuda.set_device(0)
     N, K, r, L = 2048, 1723, 32, 32
     code = synth.make_code(N, K, r, synth.CRC32_POLY, 4.0)
-    print(f"[bench] generating {args.frames} frames ({args.dtype}, {args.ebn0} dB)", file=sys.stderr,
-          flush=True)
-    b = synth.make_batch(code, args.frames, args.ebn0, (20481723, int(args.ebn0 * 100)), args.dtype)
-    llr = torch.from_numpy(b.llr).cuda()
-    plan = pk.Plan(N, K, code.frozen, code.poly, r, L, args.dtype)
-    u_hat = torch.empty((args.frames, K), dtype=torch.uint8, device="cuda")
-    crc_ok = torch.empty(args.frames, dtype=torch.uint8, device="cuda")
-    pm = torch.empty(args.frames, dtype=torch.float32 if args.dtype == "f32" else torch.int32,
-                     device="cuda")
+    print(f"[bench] generating {args.frames} frames ({args.ebn0} dB)", file=sys.stderr, flush=True)
+    b = synth.make_batch(code, args.frames, args.ebn0, (20481723, int(args.ebn0 * 100)), "f32")
+    wk = work_per_frame(pk, code, L)
 
-    for _ in range(args.warmup):
-        plan.decode(llr, u_hat, crc_ok, pm)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
+    def run(dtype):
+        """Times args.steps decodes of the whole batch in dtype; returns
+        (ms per step, kernel ms per launch, u_hat, crc_ok, plan)."""
+        host = synth.quantize(b.llr_f32, dtype)
+        llr = torch.from_numpy(host).cuda()
+        plan = pk.Plan(N, K, code.frozen, code.poly, r, L, dtype)
+        u_hat = torch.empty((args.frames, K), dtype=torch.uint8, device="cuda")
+        crc_ok = torch.empty(args.frames, dtype=torch.uint8, device="cuda")
+        pm = torch.empty(args.frames, dtype=torch.float32 if dtype == "f32" else torch.int32,
+                         device="cuda")
+        for _ in range(args.warmup):
+            plan.decode(llr, u_hat, crc_ok, pm)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            plan.decode(llr, u_hat, crc_ok, pm)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / args.steps
+        kms = float(np.mean([x.elapsed_time(y) for x, y in ev]))
+        return ms, kms, u_hat.cpu().numpy(), crc_ok.cpu().numpy(), plan, host
 
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        plan.decode(llr, u_hat, crc_ok, pm)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(bb) for a, bb in ev]))
+    legs = {}
+    for dtype in [args.dtype] + [d for d in ("i8",) if d != args.dtype and not args.single]:
+        print(f"[bench] timing {dtype}", file=sys.stderr, flush=True)
+        legs[dtype] = run(dtype)
+    ms_per_step, kernel_ms, u, ok_np, plan, host_llr = legs[args.dtype]
     value = args.frames * PAYLOAD / (ms_per_step * 1e-3) / 1e9
-
-    u = u_hat.cpu().numpy()
     fer = float((u != b.info).any(axis=1).mean())
 
-    wk = work_per_frame(pk, code, L)
     achieved = wk["total"] * args.frames / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_ELEM_OPS / 1e12
+    tpf = recorded_traffic(args.dtype)
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 2),
-            "unit": "Telem-op/s", "frac": round(achieved / peak, 5), "traffic": None,
+            "unit": "Telem-op/s", "frac": round(achieved / peak, 5),
+            "traffic": None if tpf is None else round(tpf * args.frames),
             "kernel": "pscl::decode_kernel", "kernel_ms": round(kernel_ms, 4),
-            "elem_ops_per_frame": wk["total"], "frames_per_launch": args.frames}
+            "elem_ops_per_frame": wk["total"], "frames_per_launch": args.frames,
+            "kernel_source": kernel_source_hash()}
+    extra = {}
+    for dtype, leg in legs.items():
+        if dtype == args.dtype:
+            continue
+        ms2, kms2, u2, _, plan2, _ = leg
+        extra[dtype] = {"value": round(args.frames * PAYLOAD / (ms2 * 1e-3) / 1e9, 4),
+                        "ms_per_step": round(ms2, 4), "kernel_ms": round(kms2, 4),
+                        "fer": float((u2 != b.info).any(axis=1).mean()),
+                        "roofline_frac": round(wk["total"] * args.frames / (kms2 * 1e-3) / PEAK_ELEM_OPS, 5),
+                        "launch": plan2.info()}
 
     cpu = None
     if args.cpu_sample > 0:
@@ -137,10 +207,10 @@ def main():
         th = cpu_threads()
         print(f"[bench] cpu baseline: oracle on {S} frames, {th} threads", file=sys.stderr, flush=True)
         ts = time.perf_counter()
-        ref = oracle.decode_tree(N, K, code.frozen, code.poly, r, L, b.llr[:S], args.dtype,
+        ref = oracle.decode_tree(N, K, code.frozen, code.poly, r, L, host_llr[:S], args.dtype,
                                  threads=th)
         te = time.perf_counter()
-        agree = int(((ref[0] == u[:S]).all(axis=1) & (ref[1] == crc_ok[:S].cpu().numpy())).sum())
+        agree = int(((ref[0] == u[:S]).all(axis=1) & (ref[1] == ok_np[:S])).sum())
         cpu = {"value": round(S * PAYLOAD / (te - ts) / 1e9, 6), "unit": "Gbps", "cores": th,
                "kind": "oracle",
                "sample": f"first {S} frames of the timed batch, decoder A (tree, L=32, {args.dtype})",
@@ -166,6 +236,7 @@ def main():
                    "fer": fer, "launch": info},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_dtypes": extra,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,16 +1,17 @@
 // CRC-aided list decoding of polar codes on gfx950 (MI355X).
 //
-// One workgroup decodes FW frames of the same code in lockstep: every
-// operation of the unrolled schedule (Listing 2 generalised to the list
-// decoder of Sec. III) is applied to all frames, all active paths and all
-// elements at once, spread over the workgroup's threads, with one barrier
-// between operations.  The list-decoder state of a frame lives in LDS:
+// A persistent grid of small workgroups; each decodes one frame at a time by
+// walking the code's schedule (Listing 2 generalised to the list decoder of
+// Sec. III).  Between two forking leaves every operation acts on each path
+// alone, so each path is owned by a group of lanes inside one wavefront and
+// runs without workgroup barriers; candidate ranking and the survivors'
+// write-back are the only workgroup-wide steps.  A frame's state:
 //   - LLR stages S_k (Sec. V-A): L buffers of 2^k values per stage; stage n is
-//     the channel row itself, read straight from the input.  Stages too large
-//     for the LDS budget live in a per-workgroup global workspace instead.
+//     the channel row itself.  Low stages live in LDS, stages too large for
+//     the LDS budget in a per-workgroup global workspace.
 //   - Partial-sum (beta) stages (Sec. V-B) as bit-packed words, separate for
-//     left and right children.
-//   - Per-stage path -> buffer indices: a fork shares its source's buffers by
+//     left and right children, split between LDS and workspace the same way.
+//   - Per-slot path -> buffer tables: a fork shares its source's buffers by
 //     copying indices, never data (the pointer sharing of Sec. V-A); every
 //     write goes to the writer's own slot, which is always dead data at that
 //     point of the depth-first walk.
