@@ -697,49 +697,96 @@ DEV void pp_rate0_any(const Ctx<T>& c, const OpRec& op, int k, int side, const G
     else pp_rate0<T, SP_CH, SP_WS>(c, op, k, side, q);
 }
 
-// Candidate selection, Alg. 1, over the whole workgroup: a candidate's rank
-// is the number of candidates that beat it (larger metric, or equal metric
-// and smaller enumeration index), counted by TP lanes over disjoint slices
-// and summed; ranks 0..L-1 survive, best first.
-template <typename T>
-DEV void select_rank(const Ctx<T>& c, int C, int L) {
-    const int lC = ilog2u(C);
-    int TP = c.NT >> lC;
-    TP = TP < 1 ? 1 : (TP > 64 ? 64 : TP);
-    if (C >= 8 && TP > (C >> 3)) TP = C >> 3;  // slices of at least 8 keys
-    if (C < 8) TP = 1;
-    const int lt = ilog2u(TP);
-    const int span = C >> lt;
-    const int total = 1 << (lC + lt);
-    const int wave = c.tid >> 6;
-    const uint64_t* ck = c.ckey();
-    for (int base = wave * 64; base < total; base += c.NT) {
-        const int it = base + c.lane;
-        const bool act = it < total;
-        const int itc = act ? it : total - 1;
-        const int e = itc >> lt;
-        const int t = itc & (TP - 1);
-        const uint64_t mine = ck[e];
-        const int e0 = t * span;
-        int rank = 0;
-        if (span >= 8) {
-            for (int e2 = e0; e2 < e0 + span; e2 += 8) {
-                uint4 v[4];
+// Candidate selection, Alg. 1, in one wavefront: the C ranking keys (larger
+// = better: metric, then smaller enumeration index) are sorted in descending
+// order by a bitonic network, E keys per lane (element i = lane * E + t,
+// missing elements padded with key 0, which every real key beats); the first
+// L positions are the survivors, best first.
+template <int E>
+DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int L) {
+    uint64_t v[E];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = *(const uint4*)(ck + e2 + 2 * u);
+    for (int t = 0; t < E; ++t) {
+        const int e = lane * E + t;
+        v[t] = e < C ? ck[e] : 0ull;
+    }
+    constexpr int CP = 64 * E;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint64_t a0 = ((uint64_t)v[u].y << 32) | v[u].x;
-                    const uint64_t a1 = ((uint64_t)v[u].w << 32) | v[u].z;
-                    rank += (a0 > mine ? 1 : 0) + (a1 > mine ? 1 : 0);
+    for (int k = 2; k <= CP; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+                // both elements of a pair in this lane
+#pragma unroll
+                for (int t = 0; t < E; ++t) {
+                    const int l = t ^ j;
+                    if (l > t) {
+                        const int i = lane * E + t;
+                        const bool desc = (i & k) == 0;
+                        const uint64_t hi = umax64(v[t], v[l]), lo = umin64(v[t], v[l]);
+                        v[t] = desc ? hi : lo;
+                        v[l] = desc ? lo : hi;
+                    }
+                }
+            } else {
+                // partner in lane ^ (j / E), same position
+                const int m = j / E;
+#pragma unroll
+                for (int t = 0; t < E; ++t) {
+                    const uint64_t o = shfl_xor64(v[t], m);
+                    const int i = lane * E + t;
+                    const bool want_max = ((i & k) == 0) == ((i & j) == 0);
+                    v[t] = want_max ? umax64(v[t], o) : umin64(v[t], o);
                 }
             }
-        } else {
-            for (int e2 = e0; e2 < e0 + span; ++e2) rank += ck[e2] > mine ? 1 : 0;
         }
-        for (int m = 1; m < TP; m <<= 1) rank += shfl_xor_i(rank, m);
-        if (act && t == 0 && rank < L) c.surv()[rank] = (uint16_t)e;
     }
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int pos = lane * E + t;
+        if (pos < L) surv[pos] = (uint16_t)(0xffff - (uint32_t)(v[t] & 0xffff));
+    }
+}
+
+// With P = L sources, the L rank-0 (ML) candidates all have keys at least
+// T0 = the smallest of them, so the L-th best key is at least T0 and every
+// candidate below T0 is dropped before sorting.  The candidates that remain
+// are compacted (wavefront ballots) and sorted; ties cannot occur since keys
+// carry the enumeration index.
+template <typename T>
+DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
+    if (c.tid >= 64) return;
+    const int lane = c.lane;
+    uint64_t* ck = c.ckey();
+    if (C <= 64) {
+        bitonic_select<1>(ck, c.surv(), lane, C, L);
+        return;
+    }
+    uint64_t t0 = 0ull;
+    if (P == L) {
+        uint64_t v = lane < P ? ck[lane << lc] : ~0ull;
+        for (int m = 1; m < 64; m <<= 1) v = umin64(v, shfl_xor64(v, m));
+        t0 = v;
+    }
+    // compacted in place: a chunk writes only below the end of the chunk it
+    // has just read, and the wavefront's LDS accesses complete in order
+    uint64_t* kept = ck;
+    int n = 0;
+    for (int base = 0; base < C; base += 64) {
+        const int e = base + lane;
+        const uint64_t key = e < C ? ck[e] : 0ull;
+        const bool keep = e < C && key >= t0;
+        const uint64_t bal = __ballot(keep);
+        const int pos = n + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+        if (keep) kept[pos] = key;
+        n += (int)__builtin_popcountll(bal);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (n <= 64) bitonic_select<1>(kept, c.surv(), lane, n, L);
+    else if (n <= 128) bitonic_select<2>(kept, c.surv(), lane, n, L);
+    else bitonic_select<4>(kept, c.surv(), lane, n, L);
 }
 
 // Pass 3 of a forking leaf for one destination slot j: its metric, its path
@@ -980,7 +1027,7 @@ __global__ void __launch_bounds__(1024)
                     pprune = C > c.L;
                     __syncthreads();
                     if (pprune) {
-                        select_rank<T>(c, C, c.L);
+                        select_rank<T>(c, C, c.L, P, ilog2u(cc));
                         __syncthreads();
                     }
                     P = pprune ? c.L : C;
