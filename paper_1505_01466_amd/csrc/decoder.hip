@@ -21,6 +21,7 @@
 // through a codeword-domain syndrome table, the best passing path is chosen
 // (Sec. II-B), and its bits are mapped back to u = x G_N.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cstdlib>
@@ -170,6 +171,126 @@ struct VecIO<int8_t> {
             w[t] = ((uint32_t)v[4 * t] & 0xffu) | (((uint32_t)v[4 * t + 1] & 0xffu) << 8) |
                    (((uint32_t)v[4 * t + 2] & 0xffu) << 16) | ((uint32_t)v[4 * t + 3] << 24);
         return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// F and G on a whole 16-byte chunk of stage values (both operands already
+// within the domain's range).  F uses sign(a)sign(b)min(|a|,|b|) =
+// max(min(a, b), -max(a, b)), which needs no sign or magnitude extraction.
+// G takes the chunk's partial sums in the low V bits of bb (bit j <->
+// element j).
+// ---------------------------------------------------------------------------
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+DEV s16x2 as_s16x2(uint32_t x) { return __builtin_bit_cast(s16x2, x); }
+DEV uint32_t as_u32(s16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+
+// F on two 16-bit lanes.
+DEV uint32_t f_x2(uint32_t a, uint32_t b) {
+    const s16x2 x = as_s16x2(a), y = as_s16x2(b);
+    const s16x2 lo = __builtin_elementwise_min(x, y), hi = __builtin_elementwise_max(x, y);
+    return as_u32(__builtin_elementwise_max(lo, (s16x2)0 - hi));
+}
+
+// y + x on two 16-bit lanes, saturated to [-32768, 32767], then raised to
+// at least lo.
+DEV uint32_t addsat_x2(uint32_t a, uint32_t b, short lo) {
+    const s16x2 z = __builtin_elementwise_add_sat(as_s16x2(a), as_s16x2(b));
+    return as_u32(__builtin_elementwise_max(z, (s16x2)lo));
+}
+
+// The chunk's 16 low partial-sum bits in both 16-bit halves.
+DEV uint32_t rep16(uint32_t bb) { return __builtin_amdgcn_perm(bb, bb, 0x01000100u); }
+
+template <typename T>
+struct ChunkFG;
+
+template <>
+struct ChunkFG<float> {
+    // one IEEE min / max each: exact, and a zero's sign never decides
+    // anything (hard decisions compare with < 0)
+    static DEV uint4 f(const uint4& x, const uint4& y) {
+        float o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float a = __uint_as_float(comp4(x, j)), b = __uint_as_float(comp4(y, j));
+            o[j] = __builtin_elementwise_maximum(__builtin_elementwise_minimum(a, b),
+                                                 -__builtin_elementwise_maximum(a, b));
+        }
+        return VecIO<float>::pack(o);
+    }
+    static DEV uint4 g(const uint4& x, const uint4& y, uint32_t bb) {
+        float o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t xs = comp4(x, j) ^ ((bb << (31 - j)) & 0x80000000u);
+            o[j] = __fadd_rn(__uint_as_float(comp4(y, j)), __uint_as_float(xs));
+        }
+        return VecIO<float>::pack(o);
+    }
+};
+
+template <>
+struct ChunkFG<int16_t> {
+    static DEV uint4 f(const uint4& x, const uint4& y) {
+        return make_uint4(f_x2(x.x, y.x), f_x2(x.y, y.y), f_x2(x.z, y.z), f_x2(x.w, y.w));
+    }
+    // word w holds elements 2w (low half) and 2w + 1; m = -beta per half,
+    // (x ^ m) - m = beta ? -x : x
+    static DEV uint32_t g_word(uint32_t xw, uint32_t yw, uint32_t rep, int w) {
+        const s16x2 sh = {(short)(15 - 2 * w), (short)(14 - 2 * w)};
+        const s16x2 m = (as_s16x2(rep) << sh) >> (s16x2)15;
+        const s16x2 xn = (as_s16x2(xw) ^ m) - m;
+        return addsat_x2(yw, as_u32(xn), -32767);
+    }
+    static DEV uint4 g(const uint4& x, const uint4& y, uint32_t bb) {
+        const uint32_t rep = rep16(bb);
+        return make_uint4(g_word(x.x, y.x, rep, 0), g_word(x.y, y.y, rep, 1),
+                          g_word(x.z, y.z, rep, 2), g_word(x.w, y.w, rep, 3));
+    }
+};
+
+// int8: each value v goes to the high byte of a 16-bit half (256 v), so the
+// 16-bit saturating arithmetic saturates where the byte arithmetic would,
+// and the result is the high byte.  For G the low byte carries the partial
+// sum as a mask byte B (0xff or 0): with x replaced by x ^ B, the halves
+// hold 256 x + 0 or -256 x - 1, y's hold 256 y + B, and their sum has high
+// byte y + x or y - x (low byte 0 or 254, no carry).  The clamp to -127
+// (0x8100) completes the saturation to [-127, 127].
+template <>
+struct ChunkFG<int8_t> {
+    static DEV uint32_t f_word(uint32_t xw, uint32_t yw) {
+        const uint32_t z0 = f_x2(__builtin_amdgcn_perm(0u, xw, 0x010c000cu),
+                                 __builtin_amdgcn_perm(0u, yw, 0x010c000cu));
+        const uint32_t z1 = f_x2(__builtin_amdgcn_perm(0u, xw, 0x030c020cu),
+                                 __builtin_amdgcn_perm(0u, yw, 0x030c020cu));
+        return __builtin_amdgcn_perm(z1, z0, 0x07050301u);
+    }
+    static DEV uint4 f(const uint4& x, const uint4& y) {
+        return make_uint4(f_word(x.x, y.x), f_word(x.y, y.y), f_word(x.z, y.z), f_word(x.w, y.w));
+    }
+    // word w holds elements 4w .. 4w + 3 (bytes 0 .. 3)
+    static DEV uint32_t g_word(uint32_t xw, uint32_t yw, uint32_t rep, int w) {
+        // partial sums 4w, 4w + 1 to bits 15, 31 of s1; 4w + 2, 4w + 3 to
+        // bits 15, 31 of s0; the sign-replicating selectors spread them
+        // into mask bytes
+        const s16x2 sh1 = {(short)(15 - 4 * w), (short)(14 - 4 * w)};
+        const s16x2 sh0 = {(short)(13 - 4 * w), (short)(12 - 4 * w)};
+        const uint32_t s1 = as_u32(as_s16x2(rep) << sh1);
+        const uint32_t s0 = as_u32(as_s16x2(rep) << sh0);
+        const uint32_t bm = __builtin_amdgcn_perm(s0, s1, 0x0b0a0908u);
+        const uint32_t xp = xw ^ bm;
+        const uint32_t z0 = addsat_x2(__builtin_amdgcn_perm(bm, yw, 0x01050004u),
+                                      __builtin_amdgcn_perm(bm, xp, 0x01050004u), -32512);
+        const uint32_t z1 = addsat_x2(__builtin_amdgcn_perm(bm, yw, 0x03070206u),
+                                      __builtin_amdgcn_perm(bm, xp, 0x03070206u), -32512);
+        return __builtin_amdgcn_perm(z1, z0, 0x07050301u);
+    }
+    static DEV uint4 g(const uint4& x, const uint4& y, uint32_t bb) {
+        const uint32_t rep = rep16(bb);
+        return make_uint4(g_word(x.x, y.x, rep, 0), g_word(x.y, y.y, rep, 1),
+                          g_word(x.z, y.z, rep, 2), g_word(x.w, y.w, rep, 3));
     }
 };
 
@@ -332,17 +453,25 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
             for (int u = 0; u < U; ++u) {
                 const int ch = ch0 + u * q.G;
                 if (ch >= nch) continue;
-                A x[V], y[V], o[V];
-                IO::unpack(xq[u], x);
-                IO::unpack(yq[u], y);
+                uint4 r;
+                if constexpr (ISP != SP_CH || std::is_same<T, float>::value) {
+                    // stage values are already within range
+                    if constexpr (IS_G) r = ChunkFG<T>::g(xq[u], yq[u], bb[u]);
+                    else r = ChunkFG<T>::f(xq[u], yq[u]);
+                } else {
+                    // channel values are clamped into range first
+                    A x[V], y[V], o[V];
+                    IO::unpack(xq[u], x);
+                    IO::unpack(yq[u], y);
 #pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const A xa = (ISP == SP_CH) ? D::load(x[j]) : x[j];
-                    const A ya = (ISP == SP_CH) ? D::load(y[j]) : y[j];
-                    if constexpr (IS_G) o[j] = D::g(xa, ya, (bb[u] >> j) & 1u);
-                    else o[j] = D::f(xa, ya);
+                    for (int j = 0; j < V; ++j) {
+                        const A xa = D::load(x[j]), ya = D::load(y[j]);
+                        if constexpr (IS_G) o[j] = D::g(xa, ya, (bb[u] >> j) & 1u);
+                        else o[j] = D::f(xa, ya);
+                    }
+                    r = IO::pack(o);
                 }
-                *(uint4*)(out + (ch << LOGV)) = IO::pack(o);
+                *(uint4*)(out + (ch << LOGV)) = r;
             }
         }
     } else {
