@@ -113,6 +113,44 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
                              int crc_len, int L, int dtype, int spc_max, int mode,
                              pscl_plan** out);
 
+/*
+ * Launch shape of a plan.  A zero field takes the library default for the
+ * dtype (float32: 128 threads, 20 KiB; int16: 64 threads, 10 KiB; int8: 64
+ * threads, 12 KiB, chosen by measurement at (2048,1723) L=32), which the
+ * environment variables PSCL_THREADS and PSCL_LDS_BUDGET override.
+ *   threads: threads per workgroup (one frame per workgroup): 64, 128, 256,
+ *            512 or 1024.
+ *   lds_budget: LDS bytes per workgroup for the path tables, candidate
+ *            scratch and the low tree levels' LLR stages and partial sums;
+ *            the levels that do not fit go to the global workspace.  A
+ *            budget too small for the tables alone is raised to the
+ *            hardware limit.
+ */
+typedef struct {
+    int threads;
+    int lds_budget;
+} pscl_launch_cfg;
+
+/* pscl_plan_create with an explicit launch shape (cfg may be NULL).
+ * Returns PSCL_E_INVALID for an unsupported thread count. */
+pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                                 int crc_len, int L, int dtype, int spc_max, int mode,
+                                 const pscl_launch_cfg* cfg, pscl_plan** out);
+
+/*
+ * Autotuner: times pscl_decode of the caller's F frames (llr: device, F x N,
+ * as for pscl_decode, F >= 1) under every distinct launch shape among
+ * threads in {64, 128, 256} and LDS budgets from 8 to 48 KiB, on the given
+ * stream, and writes the fastest shape to *best (and its time per call, in
+ * milliseconds, to *best_ms when not NULL).  Allocates and frees plans and
+ * output buffers while it runs, so it belongs to set-up, not to a decoding
+ * loop.  Same argument rules and errors as pscl_plan_create.
+ */
+pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                          int crc_len, int L, int dtype, int spc_max, int mode,
+                          const void* llr, int64_t F, void* stream, pscl_launch_cfg* best,
+                          float* best_ms);
+
 /* Release a plan (NULL allowed).  Synchronises the device first. */
 void pscl_plan_destroy(pscl_plan* plan);
 

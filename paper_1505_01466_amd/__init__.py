@@ -8,11 +8,13 @@ The decoder is the C-ABI library ``_lib/libpscl.so`` (declared in
 from ._binding import (  # noqa: F401
     DTYPES,
     LIB_PATH,
+    LaunchCfg,
     MODE_SCL_LEAVES,
     MODE_TREE,
     OP_NAMES,
     Plan,
     PsclError,
+    autotune,
     decode,
     lib,
     schedule,

@@ -37,6 +37,12 @@ class PsclError(RuntimeError):
         self.status = status
 
 
+class LaunchCfg(ctypes.Structure):
+    """pscl_launch_cfg: threads per workgroup and LDS budget (0 = default)."""
+
+    _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -66,6 +72,13 @@ def _load():
     lib.pscl_decode_oneshot.restype = c_int
     lib.pscl_plan_info.argtypes = [vp, ip, ip, ip, ip, ctypes.POINTER(c_i64), ip]
     lib.pscl_plan_info.restype = c_int
+    lib.pscl_plan_create_cfg.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, c_int,
+                                         c_int, ctypes.POINTER(LaunchCfg), ctypes.POINTER(vp)]
+    lib.pscl_plan_create_cfg.restype = c_int
+    lib.pscl_autotune.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, c_int, c_int,
+                                  vp, c_i64, vp, ctypes.POINTER(LaunchCfg),
+                                  ctypes.POINTER(ctypes.c_float)]
+    lib.pscl_autotune.restype = c_int
     return lib
 
 
@@ -108,7 +121,8 @@ class Plan:
     """A decoding plan on the current device (see pscl_plan_create)."""
 
     def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int,
-                 dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE):
+                 dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE,
+                 threads: int = 0, lds_budget: int = 0):
         import torch
 
         if dtype not in DTYPES:
@@ -118,8 +132,10 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device())
         fz = _mask(frozen)
         h = ctypes.c_void_p(None)
-        _check(lib.pscl_plan_create(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype], spc_max,
-                                    mode, ctypes.byref(h)), "pscl_plan_create")
+        cfg = LaunchCfg(threads, lds_budget)
+        _check(lib.pscl_plan_create_cfg(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype],
+                                        spc_max, mode, ctypes.byref(cfg), ctypes.byref(h)),
+               "pscl_plan_create_cfg")
         self._h = h
 
     def info(self) -> dict:
@@ -180,3 +196,18 @@ def decode(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr, dty
                                    llr.data_ptr(), F, u_hat.data_ptr(), crc_ok.data_ptr(),
                                    _stream_handle(llr.device)), "pscl_decode_oneshot")
     return u_hat, crc_ok
+
+
+def autotune(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr,
+             dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE):
+    """pscl_autotune on the frames llr (F x N device tensor in dtype): returns
+    ({"threads": t, "lds_budget": b}, milliseconds per decode call)."""
+    if llr.dim() != 2 or llr.shape[1] != N or not llr.is_contiguous():
+        raise ValueError(f"llr must be a contiguous F x {N} tensor")
+    fz = _mask(frozen)
+    best = LaunchCfg(0, 0)
+    ms = ctypes.c_float(0.0)
+    _check(lib.pscl_autotune(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype], spc_max, mode,
+                             llr.data_ptr(), llr.shape[0], _stream_handle(llr.device),
+                             ctypes.byref(best), ctypes.byref(ms)), "pscl_autotune")
+    return {"threads": best.threads, "lds_budget": best.lds_budget}, ms.value

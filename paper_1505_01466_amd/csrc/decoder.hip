@@ -547,22 +547,98 @@ DEV uint32_t spc_flips(int r) { return (kSpcFlips >> (4 * r)) & 0xFu; }
 DEV uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 DEV uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
-DEV uint64_t shfl_xor64(uint64_t v, int m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-DEV double shfl_xor_d(double v, int m) {
-    return __longlong_as_double((long long)shfl_xor64((uint64_t)__double_as_longlong(v), m));
-}
-DEV int shfl_xor_i(int v, int m) { return __shfl_xor(v, m, 64); }
+// ---------------------------------------------------------------------------
+// Exchanges between lanes i and i ^ M of a wavefront in VALU (DPP and the
+// permlane swaps), without the LDS round trip of a permute.  On return
+// {a, b} = {this lane's value, lane (i ^ M)'s value}, in an order that may
+// depend on the lane, which is all that compare-exchanges and symmetric
+// reductions need.  Every lane of the wavefront must be active.
+// ---------------------------------------------------------------------------
 
-template <typename S>
-DEV S shfl_xor_s(S v, int m);
-template <>
-DEV double shfl_xor_s<double>(double v, int m) { return shfl_xor_d(v, m); }
-template <>
-DEV int shfl_xor_s<int>(int v, int m) { return shfl_xor_i(v, m); }
+template <int CTRL>
+DEV uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+}
+
+template <int M>
+DEV void xpair32(uint32_t v, uint32_t& a, uint32_t& b) {
+    if constexpr (M == 1) {
+        a = v;
+        b = dpp<0xb1>(v);  // quad_perm [1,0,3,2]
+    } else if constexpr (M == 2) {
+        a = v;
+        b = dpp<0x4e>(v);  // quad_perm [2,3,0,1]
+    } else if constexpr (M == 4) {
+        a = v;
+        b = dpp<0x141>(dpp<0x1b>(v));  // (i ^ 3) ^ 7: quad_perm [3,2,1,0], row_half_mirror
+    } else if constexpr (M == 8) {
+        a = v;
+        b = dpp<0x128>(v);  // row_ror:8
+    } else if constexpr (M == 16) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = sw[0];
+        b = sw[1];
+    } else {
+        static_assert(M == 32, "lane distance");
+        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = sw[0];
+        b = sw[1];
+    }
+}
+
+template <int M>
+DEV void xpair64(uint64_t v, uint64_t& a, uint64_t& b) {
+    uint32_t al, bl, ah, bh;
+    xpair32<M>((uint32_t)v, al, bl);
+    xpair32<M>((uint32_t)(v >> 32), ah, bh);
+    a = ((uint64_t)ah << 32) | al;
+    b = ((uint64_t)bh << 32) | bl;
+}
+
+// The same for a distance m known only at run time (uniform across the
+// wavefront); after unrolling with a constant m the switch folds away.
+DEV void xpair64_dyn(uint64_t v, int m, uint64_t& a, uint64_t& b) {
+    switch (m) {
+        case 1: xpair64<1>(v, a, b); break;
+        case 2: xpair64<2>(v, a, b); break;
+        case 4: xpair64<4>(v, a, b); break;
+        case 8: xpair64<8>(v, a, b); break;
+        case 16: xpair64<16>(v, a, b); break;
+        default: xpair64<32>(v, a, b); break;
+    }
+}
+
+// Calls fn(integral_constant<M>) for M = 1, 2, 4, ... below G (G a power
+// of two, at most 64): the steps of a butterfly over groups of G lanes.
+template <typename Fn>
+DEV void xor_steps(int G, Fn&& fn) {
+    if (G > 1) fn(std::integral_constant<int, 1>{});
+    if (G > 2) fn(std::integral_constant<int, 2>{});
+    if (G > 4) fn(std::integral_constant<int, 4>{});
+    if (G > 8) fn(std::integral_constant<int, 8>{});
+    if (G > 16) fn(std::integral_constant<int, 16>{});
+    if (G > 32) fn(std::integral_constant<int, 32>{});
+}
+
+// Sum over each group of G lanes (every lane gets the group's sum).
+// Integers are exact; doubles here hold sums of single-precision values,
+// which are exact as long as they span fewer than 2^29 binades of spread.
+DEV int group_sum(int v, int G) {
+    xor_steps(G, [&](auto mc) {
+        uint32_t a, b;
+        xpair32<decltype(mc)::value>((uint32_t)v, a, b);
+        v = (int)a + (int)b;
+    });
+    return v;
+}
+DEV double group_sum(double v, int G) {
+    xor_steps(G, [&](auto mc) {
+        uint64_t a, b;
+        xpair64<decltype(mc)::value>((uint64_t)__double_as_longlong(v), a, b);
+        v = __longlong_as_double((long long)a) + __longlong_as_double((long long)b);
+    });
+    return v;
+}
 
 // The 4 smallest of two ascending 4-lists, ascending (bitonic split of a
 // against reversed b, then a 4-element bitonic merge).
@@ -666,7 +742,7 @@ DEV void pp_rate0(const Ctx<T>& c, const OpRec& op, int k, int side, const Grp& 
             if (v < 0) s += D::widen_abs(v);
         });
     }
-    for (int m = 1; m < q.G; m <<= 1) s += shfl_xor_s<S>(s, m);
+    s = group_sum(s, q.G);
     if (!q.valid) return;
     if (q.g == 0) c.pm()[q.p] = D::sub(c.pm()[q.p], D::round_pen(s));
     uint32_t* o = c.template bw<OSP>(op.y, k, q.p);
@@ -703,10 +779,8 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                 else o += D::widen_abs(v);
             });
         }
-        for (int m = 1; m < q.G; m <<= 1) {
-            z += shfl_xor_s<S>(z, m);
-            o += shfl_xor_s<S>(o, m);
-        }
+        z = group_sum(z, q.G);
+        o = group_sum(o, q.G);
         if (q.valid && q.g == 0) {
             const M zr = D::round_pen(z), orr = D::round_pen(o);
             const bool one = orr < zr;  // ML word first; equal -> all-zero
@@ -733,13 +807,14 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                     k1 = lo;
                 });
             }
-            for (int m = 1; m < q.G; m <<= 1) {
-                const uint64_t o1 = shfl_xor64(k1, m), o2 = shfl_xor64(k2, m);
-                const uint64_t n1 = umin64(k1, o1);
-                const uint64_t n2 = umin64(umax64(k1, o1), umin64(k2, o2));
-                k1 = n1;
-                k2 = n2;
-            }
+            xor_steps(q.G, [&](auto mc) {
+                constexpr int M = decltype(mc)::value;
+                uint64_t a1, b1, a2, b2;
+                xpair64<M>(k1, a1, b1);
+                xpair64<M>(k2, a2, b2);
+                k1 = umin64(a1, b1);
+                k2 = umin64(umax64(a1, b1), umin64(a2, b2));
+            });
             if (q.valid && q.g == 0) {
                 const S a1 = D::mag_from_key((uint32_t)(k1 >> 32));
                 const S a2 = D::mag_from_key((uint32_t)(k2 >> 32));
@@ -760,13 +835,16 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                 insert4(kk, ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i);
             });
         }
-        for (int m = 1; m < q.G; m <<= 1) {
+        xor_steps(q.G, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
             uint64_t ob[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) ob[t] = shfl_xor64(kk[t], m);
-            par ^= shfl_xor_i(par, m);
+            for (int t = 0; t < 4; ++t) xpair64<M>(kk[t], kk[t], ob[t]);
+            uint32_t pa, pb;
+            xpair32<M>((uint32_t)par, pa, pb);
+            par = (int)(pa ^ pb);
             merge4(kk, ob);
-        }
+        });
         if (q.valid && q.g == 0) {
             // The four positions re-sorted by index (carrying their
             // reliability rank), so penalties sum in index order.
@@ -862,10 +940,11 @@ DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int
                 const int m = j / E;
 #pragma unroll
                 for (int t = 0; t < E; ++t) {
-                    const uint64_t o = shfl_xor64(v[t], m);
+                    uint64_t pa, pb;
+                    xpair64_dyn(v[t], m, pa, pb);
                     const int i = lane * E + t;
                     const bool want_max = ((i & k) == 0) == ((i & j) == 0);
-                    v[t] = want_max ? umax64(v[t], o) : umin64(v[t], o);
+                    v[t] = want_max ? umax64(pa, pb) : umin64(pa, pb);
                 }
             }
         }
@@ -894,7 +973,11 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
     uint64_t t0 = 0ull;
     if (P == L) {
         uint64_t v = lane < P ? ck[lane << lc] : ~0ull;
-        for (int m = 1; m < 64; m <<= 1) v = umin64(v, shfl_xor64(v, m));
+        xor_steps(64, [&](auto mc) {
+            uint64_t pa, pb;
+            xpair64<decltype(mc)::value>(v, pa, pb);
+            v = umin64(pa, pb);
+        });
         t0 = v;
     }
     // compacted in place: a chunk writes only below the end of the chunk it
@@ -986,6 +1069,15 @@ DEV void pp_emit_pending(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
 // Final choice: CRC syndromes, best passing path, u = x G_N, output.
 // ---------------------------------------------------------------------------
 
+// Syndrome contribution of one 32-bit codeword word w (nb valid bits): the
+// XOR of the table rows of its set bits.
+DEV uint64_t word_syndrome(uint32_t v, const uint64_t* sy, int nb) {
+    uint64_t acc = 0;
+#pragma unroll 8
+    for (int b = 0; b < nb; ++b) acc ^= ((v >> b) & 1u) ? sy[b] : 0ull;
+    return acc;
+}
+
 template <typename T, int RSP>
 DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_hat,
                 uint8_t* crc_ok, void* pm_out) {
@@ -994,51 +1086,91 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
     const int W = words_of(n);
     const int lP = ilog2u(P);
     const int wave = c.tid >> 6;
-    // syndromes: one group of lanes per path
-    {
-        const int G = W < 64 ? W : 64;
-        const int lg = ilog2u(G);
-        const int cnt = W >> lg;
-        const int total = 1 << (lP + lg);
-        for (int base = wave * 64; base < total; base += c.NT) {
-            const int it = base + c.lane;
-            const bool act = it < total;
-            const int itc = act ? it : total - 1;
-            const int j = itc >> lg;
-            const int g = itc & (G - 1);
-            const uint32_t* x = c.template bw<RSP>(a.root_off, n, j);
-            uint64_t acc = 0;
-            if (a.has_crc) {
-                const int nb = c.N < 32 ? c.N : 32;
-                for (int t = 0; t < cnt; ++t) {
-                    const int w = g + (t << lg);
-                    const uint32_t v = x[w];
-                    const uint64_t* sy = a.syn + (w << 5);
-#pragma unroll 8
-                    for (int b = 0; b < nb; ++b) {
-                        const uint64_t tv = sy[b];
-                        acc ^= ((v >> b) & 1u) ? tv : 0ull;
-                    }
-                }
-                for (int m = 1; m < G; m <<= 1) acc ^= shfl_xor64(acc, m);
-            }
-            if (act && g == 0) c.surv()[j] = (acc == 0) ? 1 : 0;
+    const int nb = c.N < 32 ? c.N : 32;
+    // sinfo[0] = chosen slot, sinfo[1] = its CRC verdict; sinfo[4..7] one
+    // 64-bit syndrome accumulator
+    uint16_t* si = c.sinfo();
+    uint64_t* syn_acc = (uint64_t*)(si + 4);
+    // The answer is the best-metric path among those passing the CRC (ties
+    // to the lower slot).  If the best-metric path passes, that is it;
+    // only otherwise is every path's syndrome needed.
+    if (c.tid < 64) {
+        const int j = c.lane < P ? c.lane : 0;
+        uint64_t key = ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+        xor_steps(P, [&](auto mc) {
+            uint64_t pa, pb;
+            xpair64<decltype(mc)::value>(key, pa, pb);
+            key = umax64(pa, pb);
+        });
+        if (c.lane == 0) {
+            si[0] = (uint16_t)(255 - (int)(key & 0xff));
+            si[1] = 1;
+            *syn_acc = 0ull;
         }
     }
     __syncthreads();
-    // pick: one lane per path
-    if (c.tid < 64) {
-        const int j = c.lane < P ? c.lane : 0;
-        const uint64_t pass = c.surv()[j] & 1;
-        uint64_t key = (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
-        for (int m = 1; m < P; m <<= 1) key = umax64(key, shfl_xor64(key, m));
-        if (c.lane == 0) {
-            const int best = 255 - (int)(key & 0xff);
-            const int ok = (int)(key >> 40) & 1;
-            c.sinfo()[0] = (uint16_t)best;
-            if (crc_ok) crc_ok[f] = (uint8_t)ok;
-            if (pm_out) ((uint32_t*)pm_out)[f] = D::bits(c.pm()[best]);
+    if (a.has_crc) {
+        {
+            const uint32_t* x = c.template bw<RSP>(a.root_off, n, si[0]);
+            uint64_t acc = 0;
+            for (int w = c.tid; w < W; w += c.NT) acc ^= word_syndrome(x[w], a.syn + (w << 5), nb);
+            xor_steps(64, [&](auto mc) {
+                uint64_t pa, pb;
+                xpair64<decltype(mc)::value>(acc, pa, pb);
+                acc = pa ^ pb;
+            });
+            if (c.lane == 0 && acc) atomicXor((unsigned long long*)syn_acc, (unsigned long long)acc);
         }
+        __syncthreads();
+        if (*syn_acc != 0ull) {
+            // every path's syndrome: one group of lanes per path
+            const int G = W < 64 ? W : 64;
+            const int lg = ilog2u(G);
+            const int cnt = W >> lg;
+            const int total = 1 << (lP + lg);
+            for (int base = wave * 64; base < total; base += c.NT) {
+                const int it = base + c.lane;
+                const bool act = it < total;
+                const int itc = act ? it : total - 1;
+                const int j = itc >> lg;
+                const int g = itc & (G - 1);
+                const uint32_t* x = c.template bw<RSP>(a.root_off, n, j);
+                uint64_t acc = 0;
+                for (int t = 0; t < cnt; ++t) {
+                    const int w = g + (t << lg);
+                    acc ^= word_syndrome(x[w], a.syn + (w << 5), nb);
+                }
+                xor_steps(G, [&](auto mc) {
+                    uint64_t pa, pb;
+                    xpair64<decltype(mc)::value>(acc, pa, pb);
+                    acc = pa ^ pb;
+                });
+                if (act && g == 0) c.surv()[j] = (acc == 0) ? 1 : 0;
+            }
+            __syncthreads();
+            // pick: one lane per path
+            if (c.tid < 64) {
+                const int j = c.lane < P ? c.lane : 0;
+                const uint64_t pass = c.surv()[j] & 1;
+                uint64_t key =
+                    (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+                xor_steps(P, [&](auto mc) {
+                    uint64_t pa, pb;
+                    xpair64<decltype(mc)::value>(key, pa, pb);
+                    key = umax64(pa, pb);
+                });
+                if (c.lane == 0) {
+                    si[0] = (uint16_t)(255 - (int)(key & 0xff));
+                    si[1] = (uint16_t)((key >> 40) & 1);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (c.tid == 0) {
+        const int best = si[0];
+        if (crc_ok) crc_ok[f] = (uint8_t)si[1];
+        if (pm_out) ((uint32_t*)pm_out)[f] = D::bits(c.pm()[best]);
     }
     __syncthreads();
     // u = x G_N on the chosen codeword, in place: bits within words ...
@@ -1314,6 +1446,19 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
 
 }  // namespace
 
+// Default launch shape per dtype (measured at (2048,1723) L=32): few waves
+// per frame, since every schedule operation costs each wave its control
+// overhead and more resident frames per CU hide each frame's dependent
+// chain better than more waves per frame; an LDS budget that keeps the
+// levels up to 2^5..2^6 on chip without lowering the number of resident
+// workgroups.  PSCL_THREADS / PSCL_LDS_BUDGET override.
+static void default_launch(int dtype, int& threads, int& budget) {
+    threads = dtype == PSCL_F32 ? 128 : 64;
+    budget = dtype == PSCL_F32 ? 20 * 1024 : (dtype == PSCL_I16 ? 10 * 1024 : 12 * 1024);
+    if (const char* e = getenv("PSCL_THREADS")) threads = atoi(e);
+    if (const char* e = getenv("PSCL_LDS_BUDGET")) budget = atoi(e);
+}
+
 extern "C" {
 
 const char* pscl_status_str(pscl_status s) {
@@ -1368,10 +1513,23 @@ void pscl_plan_destroy(pscl_plan* p) {
 pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
                              int crc_len, int L, int dtype, int spc_max, int mode,
                              pscl_plan** out) {
+    return pscl_plan_create_cfg(N, K, frozen_mask, crc_poly, crc_len, L, dtype, spc_max, mode,
+                                nullptr, out);
+}
+
+pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                                 int crc_len, int L, int dtype, int spc_max, int mode,
+                                 const pscl_launch_cfg* cfg, pscl_plan** out) {
     if (!out || !frozen_mask) return PSCL_E_INVALID;
     if (N < 2 || N > 4096 || (N & (N - 1))) return PSCL_E_INVALID;
     if (!valid_L(L) || dtype < PSCL_F32 || dtype > PSCL_I8) return PSCL_E_INVALID;
     if (mode != PSCL_MODE_TREE && mode != PSCL_MODE_SCL_LEAVES) return PSCL_E_INVALID;
+    int NT = 0, budget = 0;
+    default_launch(dtype, NT, budget);
+    if (cfg && cfg->threads) NT = cfg->threads;
+    if (cfg && cfg->lds_budget) budget = cfg->lds_budget;
+    if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
+    if (budget < 0) return PSCL_E_INVALID;
     int kk = 0;
     for (int i = 0; i < N; ++i) kk += frozen_mask[i] ? 0 : 1;
     if (kk != K || K < 1 || crc_len < 0 || crc_len > 64 || crc_len > K) return PSCL_E_INVALID;
@@ -1404,8 +1562,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     const int lds_hw = (int)std::min<size_t>(prop.sharedMemPerBlock, 160 * 1024);
     // A small budget keeps many frames resident per CU (their dependent
     // chains overlap); the top stages then live in the workspace.
-    int lds_cap = std::min(lds_hw, 12 * 1024);
-    if (const char* e = getenv("PSCL_LDS_BUDGET")) lds_cap = std::max(4096, std::min(lds_hw, atoi(e)));
+    int lds_cap = std::max(4096, std::min(lds_hw, budget));
     Layout lay;
     KArgs a{};
     int k_glob = p->n + 1;
@@ -1431,14 +1588,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
     }
     const int64_t wsf = lay.ws_frame;
     p->lds_bytes = bytes + sched_need;
-    // Few waves per frame: every schedule operation costs each of them its
-    // control overhead, and more resident frames per CU hide the latency of
-    // each frame's dependent chain better than more waves per frame.
-    p->NT = dtype == PSCL_F32 ? 128 : 64;
-    if (const char* e = getenv("PSCL_THREADS")) {
-        const int t = atoi(e);
-        if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) p->NT = t;
-    }
+    p->NT = NT;
     p->kernel = kernel_for(dtype);
 
     hipError_t e = hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1562,6 +1712,68 @@ pscl_status pscl_decode_oneshot(int N, int K, const uint8_t* frozen_mask, uint64
         }
     }
     return pscl_decode(p, llr, F, u_hat, crc_ok, nullptr, stream);
+}
+
+pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                          int crc_len, int L, int dtype, int spc_max, int mode,
+                          const void* llr, int64_t F, void* stream, pscl_launch_cfg* best,
+                          float* best_ms) {
+    if (!best || !llr || F < 1) return PSCL_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* u = nullptr;
+    uint8_t* ok = nullptr;
+    void* pm = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pscl_status st = hip_status(hipMalloc((void**)&u, (size_t)F * (size_t)std::max(K, 1)));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&ok, (size_t)F));
+    if (st == PSCL_OK) st = hip_status(hipMalloc(&pm, (size_t)F * 4));
+    if (st == PSCL_OK) st = hip_status(hipEventCreate(&e0));
+    if (st == PSCL_OK) st = hip_status(hipEventCreate(&e1));
+    float best_t = -1.f;
+    std::vector<std::tuple<int, int, int>> seen;  // threads, LDS bytes, workgroups
+    const int threads[] = {64, 128, 256};
+    const int budgets[] = {8192, 10240, 12288, 16384, 20480, 24576, 32768, 49152};
+    for (int t : threads) {
+        for (int b : budgets) {
+            if (st != PSCL_OK) break;
+            pscl_launch_cfg cfg{t, b};
+            pscl_plan* p = nullptr;
+            pscl_status cs = pscl_plan_create_cfg(N, K, frozen_mask, crc_poly, crc_len, L, dtype,
+                                                  spc_max, mode, &cfg, &p);
+            if (cs != PSCL_OK) {
+                if (cs == PSCL_E_UNSUPPORTED || cs == PSCL_E_NOMEM) continue;
+                st = cs;
+                break;
+            }
+            const std::tuple<int, int, int> key{p->NT, p->lds_bytes, p->grid_max};
+            if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
+                pscl_plan_destroy(p);
+                continue;
+            }
+            seen.push_back(key);
+            st = pscl_decode(p, llr, F, u, ok, pm, stream);  // warm-up
+            if (st == PSCL_OK) st = hip_status(hipEventRecord(e0, s));
+            for (int r = 0; r < 2 && st == PSCL_OK; ++r) st = pscl_decode(p, llr, F, u, ok, pm, stream);
+            if (st == PSCL_OK) st = hip_status(hipEventRecord(e1, s));
+            if (st == PSCL_OK) st = hip_status(hipEventSynchronize(e1));
+            float ms = 0.f;
+            if (st == PSCL_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+            pscl_plan_destroy(p);
+            ms *= 0.5f;
+            if (st == PSCL_OK && (best_t < 0.f || ms < best_t)) {
+                best_t = ms;
+                *best = cfg;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(u);
+    (void)hipFree(ok);
+    (void)hipFree(pm);
+    if (st == PSCL_OK && best_t < 0.f) st = PSCL_E_UNSUPPORTED;
+    if (st == PSCL_OK && best_ms) *best_ms = best_t;
+    return st;
 }
 
 }  // extern "C"

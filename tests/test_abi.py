@@ -140,3 +140,23 @@ def test_plan_create_validates_before_touching_the_device(pk):
 
 def test_decode_rejects_null_plan(pk):
     assert pk.lib.pscl_decode(None, None, 0, None, None, None, None) == 1
+
+
+def test_launch_cfg_and_autotune_validate_arguments(pk):
+    frozen = np.zeros(8, np.uint8)
+    frozen[:4] = 1
+    h = ctypes.c_void_p()
+    u8 = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    for threads in (32, 96, 2048, -64):
+        cfg = pk.LaunchCfg(threads, 0)
+        assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(cfg),
+                                           ctypes.byref(h)) == 1
+    cfg = pk.LaunchCfg(64, -1)
+    assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(cfg),
+                                       ctypes.byref(h)) == 1
+    assert not h.value
+    best = pk.LaunchCfg(0, 0)
+    # no output, no frames, no input
+    assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, None, None) == 1
+    assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, ctypes.byref(best),
+                                None) == 1

@@ -65,6 +65,36 @@ def test_small_codes(dtype, N):
 # (1024,860) CRC-32 L in {2..32}.
 # ---------------------------------------------------------------------------
 
+def _best_metric_fails_crc(code, L, llr, dtype):
+    """Frames whose best-metric final path fails the CRC while another
+    path passes (from the oracle's final list), so that the decoder has to
+    fall back to a lower-metric path."""
+    import oracle
+
+    info = np.flatnonzero(code.frozen == 0)
+    out = []
+    for f in range(llr.shape[0]):
+        cw, pm = oracle.decode_tree_list(code.N, code.K, code.frozen, L, llr[f], dtype)
+        best = int(np.argsort(-pm, kind="stable")[0])
+        ok = [oracle.crc(oracle.polar_transform(cw[j])[info], code.poly, code.r) == 0
+              for j in range(cw.shape[0])]
+        if not ok[best] and any(ok):
+            out.append(f)
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_crc_pick_below_the_best_metric(dtype):
+    code, b = batch(256, 128, 8, synth.CRC8_POLY, 2.0, 300, 1.5, (7, 1), dtype)
+    frames = _best_metric_fails_crc(code, 8, b.llr, dtype)
+    _say(f"(256,128) L=8 {dtype}: {len(frames)} frames pick below the best metric")
+    assert len(frames) >= 10
+    g = gpu_decode(code, 8, b.llr, dtype)
+    o = oracle_decode(code, 8, b.llr, dtype)
+    compare(g, o, dtype, f"(256,128) L=8 {dtype} fallback pick")
+    assert o[1][frames].all()  # each of those frames does find a passing path
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_1024_512_crc8_L4_f32(mode):
     code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 2000, 2.5, (1, mode), "f32")
@@ -175,3 +205,18 @@ def test_oneshot_entry_point():
     torch.cuda.synchronize()
     o = oracle_decode(code, 8, b.llr, "i16")
     assert (u.cpu().numpy() == o[0]).all() and (ok.cpu().numpy() == o[1]).all()
+
+
+def test_autotuned_launch_shape():
+    import paper_1505_01466_amd as pk
+    import torch
+
+    code, b = batch(512, 256, 8, synth.CRC8_POLY, 2.5, 512, 2.5, (9, 1), "i8")
+    llr = torch.from_numpy(b.llr).cuda()
+    cfg, ms = pk.autotune(code.N, code.K, code.frozen, code.poly, code.r, 8, llr, "i8")
+    _say(f"(512,256) L=8 i8 autotuned {cfg} {ms:.3f} ms")
+    assert cfg["threads"] in (64, 128, 256) and 8192 <= cfg["lds_budget"] <= 49152 and ms > 0
+    plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 8, "i8", **cfg)
+    assert plan.info()["threads"] == cfg["threads"]
+    g = gpu_decode(code, 8, b.llr, "i8", plan=plan)
+    compare(g, oracle_decode(code, 8, b.llr, "i8"), "i8", "autotuned plan")
