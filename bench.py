@@ -91,6 +91,17 @@ def recorded_traffic(dtype):
     return float(vals[key]) if key in vals else None
 
 
+def wilson(k, n, z=1.959964):
+    """Wilson score 95% interval of a binomial proportion k / n."""
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * ((p * (1 - p) / n + z * z / (4 * n * n)) ** 0.5) / d
+    return (max(0.0, c - h), min(1.0, c + h))
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -107,7 +118,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "i16", "i8"])
     ap.add_argument("--frames", type=int, default=65536, help="frames per step")
     ap.add_argument("--ebn0", type=float, default=4.0)
-    ap.add_argument("--cpu-sample", type=int, default=8192,
+    ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="frames the oracle decodes for the CPU baseline (0 = skip)")
     ap.add_argument("--single", action="store_true", help="time only --dtype")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -211,14 +222,21 @@ def main():
                                  threads=th)
         te = time.perf_counter()
         agree = int(((ref[0] == u[:S]).all(axis=1) & (ref[1] == ok_np[:S])).sum())
+        k_or = int((ref[0] != b.info[:S]).any(axis=1).sum())
+        k_gpu = int((u[:S] != b.info[:S]).any(axis=1).sum())
+        lo, hi = wilson(k_or, S)
+        fer_cmp = {"frames": S, "oracle": k_or / S, "oracle_ci95": [round(lo, 6), round(hi, 6)],
+                   "gpu": k_gpu / S, "gpu_inside_ci": bool(lo <= k_gpu / S <= hi)}
         cpu = {"value": round(S * PAYLOAD / (te - ts) / 1e9, 6), "unit": "Gbps", "cores": th,
                "kind": "oracle",
                "sample": f"first {S} frames of the timed batch, decoder A (tree, L=32, {args.dtype})",
-               "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}"}
+               "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
+               "fer_vs_oracle": fer_cmp}
 
     info = plan.info()
     out = {
         "metric": "info Gbps @ (2048,1723) CRC32 L=32",
+        "fer_vs_oracle": None if cpu is None else cpu["fer_vs_oracle"],
         "value": round(value, 4),
         "unit": "Gbps",
         "n_gpus": 1,
