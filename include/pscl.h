@@ -28,7 +28,10 @@
  *
  * Ownership: the caller owns every device buffer passed in; a plan owns its
  * device schedule, tables and workspace.  Decoding is asynchronous on the
- * caller's HIP stream and never allocates.  All device pointers must be
+ * caller's HIP stream and never allocates.  A plan's workspace serves one
+ * call at a time: calls on one plan must be ordered (one stream, or
+ * synchronised); a group (below) keeps a workspace per call in flight, so
+ * its calls may overlap on different streams.  All device pointers must be
  * accessible from the device that was current when the plan was created.
  *
  * Errors: every function returns a status code and never throws.  A HIP
@@ -179,6 +182,60 @@ pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8
 pscl_status pscl_decode_oneshot(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
                                 int crc_len, int L, int dtype, const void* llr, int64_t F,
                                 uint8_t* u_hat, uint8_t* crc_ok, void* stream);
+
+/*
+ * Mixed launches: frames of several codes (N, K, L, CRC) of one dtype in one
+ * persistent launch.  Workgroups take frames one at a time from a device
+ * counter, most expensive code first, so frames of very different cost
+ * share the GPU without a tail per code.
+ *
+ * A job is F frames of plans[plan] with its own buffers, each with the
+ * layout and rules of pscl_decode (llr 16-byte aligned; crc_ok, pm may be
+ * NULL).  Jobs with F = 0 are skipped.
+ */
+typedef struct {
+    int plan;
+    const void* llr;
+    int64_t F;
+    uint8_t* u_hat;
+    uint8_t* crc_ok;
+    void* pm;
+} pscl_job;
+
+typedef struct pscl_group pscl_group;
+
+/*
+ * A group of plans decoded together.  All plans must have one dtype and
+ * belong to the current device (PSCL_E_UNSUPPORTED / PSCL_E_INVALID
+ * otherwise) and must outlive the group.  max_jobs bounds the non-empty
+ * jobs of one call.  cfg (NULL allowed) sets the threads per workgroup;
+ * each plan keeps its own LDS layout, and the launch reserves the largest.
+ * Allocates the concatenated schedules and, per call in flight, a workspace
+ * for the largest plan and a pinned job table, so pscl_group_decode never
+ * allocates.
+ */
+pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int max_jobs,
+                              const pscl_launch_cfg* cfg, pscl_group** out);
+
+/* Release a group (NULL allowed) after its launches have finished. */
+void pscl_group_destroy(pscl_group* group);
+
+/*
+ * Decode the jobs in one launch on the stream (asynchronous).  Up to four
+ * calls may be in flight per group, on any streams (each has its own job
+ * table and workspace); a fifth waits on the host for the first to finish.  Returns PSCL_E_INVALID for a bad plan index, F < 0,
+ * null or misaligned required pointers, or more than max_jobs non-empty
+ * jobs.  Results are identical to pscl_decode of each job with its plan.
+ */
+pscl_status pscl_group_decode(pscl_group* group, const pscl_job* jobs, int n_jobs, void* stream);
+
+/*
+ * The same without an explicit group: the group for this list of plans is
+ * created on first use (allocating) and cached until one of its plans is
+ * destroyed.
+ */
+pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
+                              int n_jobs, void* stream);
 
 /* Launch shape chosen for a plan: frames per workgroup, threads per
  * workgroup, workgroups, LDS bytes per workgroup, bytes of global workspace,

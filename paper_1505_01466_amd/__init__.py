@@ -8,6 +8,8 @@ The decoder is the C-ABI library ``_lib/libpscl.so`` (declared in
 from ._binding import (  # noqa: F401
     DTYPES,
     LIB_PATH,
+    Group,
+    Job,
     LaunchCfg,
     MODE_SCL_LEAVES,
     MODE_TREE,
@@ -16,6 +18,7 @@ from ._binding import (  # noqa: F401
     PsclError,
     autotune,
     decode,
+    decode_mixed,
     lib,
     schedule,
 )

@@ -43,6 +43,13 @@ class LaunchCfg(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int)]
 
 
+class Job(ctypes.Structure):
+    """pscl_job: F frames of plans[plan] with their own device buffers."""
+
+    _fields_ = [("plan", ctypes.c_int), ("llr", ctypes.c_void_p), ("F", ctypes.c_int64),
+                ("u_hat", ctypes.c_void_p), ("crc_ok", ctypes.c_void_p), ("pm", ctypes.c_void_p)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -79,6 +86,15 @@ def _load():
                                   vp, c_i64, vp, ctypes.POINTER(LaunchCfg),
                                   ctypes.POINTER(ctypes.c_float)]
     lib.pscl_autotune.restype = c_int
+    lib.pscl_group_create.argtypes = [ctypes.POINTER(vp), c_int, c_int, ctypes.POINTER(LaunchCfg),
+                                      ctypes.POINTER(vp)]
+    lib.pscl_group_create.restype = c_int
+    lib.pscl_group_destroy.argtypes = [vp]
+    lib.pscl_group_destroy.restype = None
+    lib.pscl_group_decode.argtypes = [vp, ctypes.POINTER(Job), c_int, vp]
+    lib.pscl_group_decode.restype = c_int
+    lib.pscl_decode_mixed.argtypes = [ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), c_int, vp]
+    lib.pscl_decode_mixed.restype = c_int
     return lib
 
 
@@ -211,3 +227,69 @@ def autotune(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr,
                              llr.data_ptr(), llr.shape[0], _stream_handle(llr.device),
                              ctypes.byref(best), ctypes.byref(ms)), "pscl_autotune")
     return {"threads": best.threads, "lds_budget": best.lds_budget}, ms.value
+
+
+def _jobs(plans, work):
+    """Marshals [(plan index, llr tensor), ...] into pscl_job entries with
+    freshly allocated outputs; returns (ctypes array, outputs)."""
+    import torch
+
+    arr = (Job * max(1, len(work)))()
+    outs = []
+    for i, (pi, llr) in enumerate(work):
+        pl = plans[pi]
+        want = {"f32": torch.float32, "i16": torch.int16, "i8": torch.int8}[pl.dtype]
+        if llr.dtype != want or llr.dim() != 2 or llr.shape[1] != pl.N or not llr.is_contiguous():
+            raise ValueError(f"job {i}: llr must be a contiguous F x {pl.N} {want} tensor")
+        F = llr.shape[0]
+        u = torch.empty((F, pl.K), dtype=torch.uint8, device=llr.device)
+        ok = torch.empty(F, dtype=torch.uint8, device=llr.device)
+        pm = torch.empty(F, dtype=torch.float32 if pl.dtype == "f32" else torch.int32,
+                         device=llr.device)
+        arr[i] = Job(pi, llr.data_ptr(), F, u.data_ptr(), ok.data_ptr(), pm.data_ptr())
+        outs.append((u, ok, pm))
+    return arr, outs
+
+
+class Group:
+    """A group of plans of one dtype decoded together in one persistent
+    launch (see pscl_group_create); the plans must outlive it."""
+
+    def __init__(self, plans, max_jobs: int = 64, threads: int = 0):
+        self.plans = list(plans)
+        hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        cfg = LaunchCfg(threads, 0)
+        h = ctypes.c_void_p(None)
+        _check(lib.pscl_group_create(hs, len(self.plans), max_jobs, ctypes.byref(cfg),
+                                     ctypes.byref(h)), "pscl_group_create")
+        self._h = h
+
+    def decode(self, work):
+        """work: [(plan index, llr F x N device tensor), ...] -> [(u_hat, crc_ok, pm), ...]."""
+        arr, outs = _jobs(self.plans, work)
+        dev = self.plans[0].device
+        _check(lib.pscl_group_decode(self._h, arr, len(work), _stream_handle(dev)),
+               "pscl_group_decode")
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pscl_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode_mixed(plans, work):
+    """pscl_decode_mixed: the group for this list of plans is cached by the
+    library.  work: [(plan index, llr tensor), ...] -> [(u_hat, crc_ok, pm), ...]."""
+    plans = list(plans)
+    hs = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    arr, outs = _jobs(plans, work)
+    _check(lib.pscl_decode_mixed(hs, len(plans), arr, len(work), _stream_handle(plans[0].device)),
+           "pscl_decode_mixed")
+    return outs

@@ -1205,9 +1205,108 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
 }
 
 // ---------------------------------------------------------------------------
-// The kernel: a persistent grid; each workgroup decodes one frame at a time.
+// One frame through the whole schedule, by the whole workgroup.
 // ---------------------------------------------------------------------------
 
+// Points the context at a plan's LDS layout and workspace region.
+template <typename T>
+DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
+    c.wsb = wsb;
+    c.N = a.N;
+    c.n = a.n;
+    c.L = a.L;
+    c.ptrA_off = a.ptrA_off;
+    c.ptrB_off = a.ptrB_off;
+    c.pm_off = a.pm_off;
+    c.cpm_off = a.cpm_off;
+    c.ckey_off = a.ckey_off;
+    c.surv_off = a.surv_off;
+    c.sinfo_off = a.sinfo_off;
+}
+
+// Schedule records are read with scalar loads (sched points into a
+// read-only kernel argument), the next one while the current operation
+// runs.  Outputs go to entry f of u_hat / crc_ok / pm_out.
+template <typename T>
+DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sched, int64_t f,
+                      uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
+                      void* __restrict__ pm_out) {
+    c.cur = 0;
+    if (c.tid == 0) c.pm()[0] = 0;
+    __syncthreads();
+    int P = 1;
+    Grp q = make_grp(c.tid, c.NT, P);
+    // a fork whose survivors still have to be written (pass 3)
+    int pend = 0;
+    OpRec pop{};
+    int pprune = 0;
+    uint64_t nraw = sched[0];
+    for (int oi = 0; oi < a.n_ops; ++oi) {
+        const uint64_t raw = nraw;
+        nraw = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
+        OpRec op;
+        op.meta = (uint16_t)raw;
+        op.x = (uint16_t)(raw >> 16);
+        op.y = (uint16_t)(raw >> 32);
+        op.z = (uint16_t)(raw >> 48);
+        const int type = op_type(op);
+        const int k = op_k(op);
+        const int side = op_side(op);
+        const int cc = op_cand(op);
+        if (pend) {
+            // every survivor is written before any path's next operation
+            // overwrites a stage buffer or the candidate scratch
+            pp_emit_pending<T>(c, pop, pprune, q);
+            pend = 0;
+            __syncthreads();
+        }
+        switch (type) {
+            case OP_F:
+                pp_fg_any<T, false>(c, op, k, q);
+                break;
+            case OP_G:
+                pp_fg_any<T, true>(c, op, k, q);
+                break;
+            case OP_COMB:
+                pp_comb_any<T>(c, op, k, side, q);
+                break;
+            case OP_R0:
+                pp_rate0_any<T>(c, op, k, side, q);
+                break;
+            default: {
+                // a forking leaf: score, select across the workgroup, and
+                // leave the survivors to be written by their new owners
+                if (type == OP_REP) pp_fork_score_any<T, OP_REP>(c, op, k, cc, q);
+                else if (type == OP_R1) pp_fork_score_any<T, OP_R1>(c, op, k, cc, q);
+                else pp_fork_score_any<T, OP_SPC>(c, op, k, cc, q);
+                const int C = P * cc;
+                pprune = C > c.L;
+                __syncthreads();
+                if (pprune) {
+                    select_rank<T>(c, C, c.L, P, ilog2u(cc));
+                    __syncthreads();
+                }
+                P = pprune ? c.L : C;
+                q = make_grp(c.tid, c.NT, P);
+                pend = 1;
+                pop = op;
+                break;
+            }
+        }
+        wave_sync();
+    }
+    if (pend) pp_emit_pending<T>(c, pop, pprune, q);
+    __syncthreads();
+    if (a.root_sp == SP_LDS) finish<T, SP_LDS>(c, a, P, f, u_hat, crc_ok, pm_out);
+    else finish<T, SP_WS>(c, a, P, f, u_hat, crc_ok, pm_out);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// The kernels: persistent grids; each workgroup decodes one frame at a time.
+// ---------------------------------------------------------------------------
+
+// One code: frames blockIdx.x, blockIdx.x + gridDim.x, ...
 template <typename T>
 __global__ void __launch_bounds__(1024)
     decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
@@ -1216,97 +1315,72 @@ __global__ void __launch_bounds__(1024)
     extern __shared__ __align__(16) unsigned char lds[];
     Ctx<T> c;
     c.lds = lds;
-    c.wsb = a.ws + (int64_t)blockIdx.x * a.ws_frame;
-    c.N = a.N;
-    c.n = a.n;
-    c.L = a.L;
     c.tid = threadIdx.x;
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
-    c.ptrA_off = a.ptrA_off;
-    c.ptrB_off = a.ptrB_off;
-    c.pm_off = a.pm_off;
-    c.cpm_off = a.cpm_off;
-    c.ckey_off = a.ckey_off;
-    c.surv_off = a.surv_off;
-    c.sinfo_off = a.sinfo_off;
-
-    // Schedule records are read with scalar loads (the schedule is a
-    // read-only argument), the next one while the current operation runs.
-
+    bind_plan(c, a, a.ws + (int64_t)blockIdx.x * a.ws_frame);
     for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
         c.chan = llr + f * a.N;
-        c.cur = 0;
-        if (c.tid == 0) c.pm()[0] = 0;
-        __syncthreads();
-        int P = 1;
-        Grp q = make_grp(c.tid, c.NT, P);
-        // a fork whose survivors still have to be written (pass 3)
-        int pend = 0;
-        OpRec pop{};
-        int pprune = 0;
-        uint64_t nraw = sched[0];
-        for (int oi = 0; oi < a.n_ops; ++oi) {
-            const uint64_t raw = nraw;
-            nraw = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
-            OpRec op;
-            op.meta = (uint16_t)raw;
-            op.x = (uint16_t)(raw >> 16);
-            op.y = (uint16_t)(raw >> 32);
-            op.z = (uint16_t)(raw >> 48);
-            const int type = op_type(op);
-            const int k = op_k(op);
-            const int side = op_side(op);
-            const int cc = op_cand(op);
-            if (pend) {
-                // every survivor is written before any path's next operation
-                // overwrites a stage buffer or the candidate scratch
-                pp_emit_pending<T>(c, pop, pprune, q);
-                pend = 0;
-                __syncthreads();
-            }
-            switch (type) {
-                case OP_F:
-                    pp_fg_any<T, false>(c, op, k, q);
-                    break;
-                case OP_G:
-                    pp_fg_any<T, true>(c, op, k, q);
-                    break;
-                case OP_COMB:
-                    pp_comb_any<T>(c, op, k, side, q);
-                    break;
-                case OP_R0:
-                    pp_rate0_any<T>(c, op, k, side, q);
-                    break;
-                default: {
-                    // a forking leaf: score, select across the workgroup, and
-                    // leave the survivors to be written by their new owners
-                    if (type == OP_REP) pp_fork_score_any<T, OP_REP>(c, op, k, cc, q);
-                    else if (type == OP_R1) pp_fork_score_any<T, OP_R1>(c, op, k, cc, q);
-                    else pp_fork_score_any<T, OP_SPC>(c, op, k, cc, q);
-                    const int C = P * cc;
-                    pprune = C > c.L;
-                    __syncthreads();
-                    if (pprune) {
-                        select_rank<T>(c, C, c.L, P, ilog2u(cc));
-                        __syncthreads();
-                    }
-                    P = pprune ? c.L : C;
-                    q = make_grp(c.tid, c.NT, P);
-                    pend = 1;
-                    pop = op;
-                    break;
-                }
-            }
-            wave_sync();
-        }
-        if (pend) pp_emit_pending<T>(c, pop, pprune, q);
-        __syncthreads();
-        if (a.root_sp == SP_LDS) finish<T, SP_LDS>(c, a, P, f, u_hat, crc_ok, pm_out);
-        else finish<T, SP_WS>(c, a, P, f, u_hat, crc_ok, pm_out);
-        __syncthreads();
+        decode_frame(c, a, sched, f, u_hat, crc_ok, pm_out);
     }
 }
+
+// Several codes of one dtype in one launch.  Plan p's schedule starts at
+// record op_base of the concatenated schedules; job j covers global frames
+// [base, base + F) of plan `plan`, with its own input and output buffers.
+struct DevPlan {
+    KArgs a;
+    int64_t op_base;
+};
+struct DevJob {
+    const void* llr;
+    uint8_t* u_hat;
+    uint8_t* crc_ok;
+    void* pm;
+    int64_t F, base;
+    int plan, pad;
+};
+
+// Frames are handed out one at a time from a counter (vector atomics), so
+// that frames of very different cost balance across workgroups; every
+// workgroup leaves once the counter has passed the last frame.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    decode_mixed_kernel(const DevPlan* __restrict__ plans, const DevJob* __restrict__ jobs,
+                        int n_jobs, int64_t total, const uint64_t* __restrict__ sched,
+                        uint8_t* __restrict__ ws, int64_t ws_frame,
+                        unsigned long long* __restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ long long next_frame;
+    Ctx<T> c;
+    c.lds = lds;
+    c.tid = threadIdx.x;
+    c.NT = blockDim.x;
+    c.lane = threadIdx.x & 63;
+    uint8_t* wsb = ws + (int64_t)blockIdx.x * ws_frame;
+    for (;;) {
+        if (c.tid == 0) next_frame = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t g = next_frame;
+        __syncthreads();
+        if (g >= total) break;
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].base <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const DevJob& J = jobs[lo];
+        const DevPlan& D = plans[J.plan];
+        const KArgs a = D.a;
+        const int64_t f = g - J.base;
+        bind_plan(c, a, wsb);
+        c.chan = (const T*)J.llr + f * a.N;
+        decode_frame(c, a, sched + D.op_base, f, J.u_hat, J.crc_ok, J.pm);
+    }
+}
+
+__global__ void zero_counter(unsigned long long* counter) { *counter = 0ull; }
 
 // ---------------------------------------------------------------------------
 // Host side.
@@ -1333,6 +1407,24 @@ struct pscl_plan {
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int64_t ws_bytes = 0;
     const void* kernel = nullptr;
+};
+
+struct pscl_group {
+    static constexpr int SLOTS = 4;  // job tables in flight
+    int device = 0, dtype = 0, NT = 64, lds_bytes = 0, grid = 0, max_jobs = 0;
+    int64_t ws_frame = 0;
+    std::vector<const pscl_plan*> plans;
+    std::vector<double> cost;  // relative work per frame, for ordering jobs
+    uint64_t* d_sched = nullptr;
+    DevPlan* d_plans = nullptr;
+    uint8_t* d_ws[SLOTS] = {};  // one workspace per call in flight
+    DevJob* d_jobs[SLOTS] = {};
+    DevJob* h_jobs[SLOTS] = {};  // pinned staging
+    unsigned long long* d_counter[SLOTS] = {};
+    hipEvent_t ev[SLOTS] = {};
+    bool used[SLOTS] = {};
+    int next_slot = 0;
+    std::mutex mu;
 };
 
 namespace {
@@ -1452,6 +1544,27 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
 // chain better than more waves per frame; an LDS budget that keeps the
 // levels up to 2^5..2^6 on chip without lowering the number of resident
 // workgroups.  PSCL_THREADS / PSCL_LDS_BUDGET override.
+// Groups made by pscl_decode_mixed for a set of plans, kept until one of
+// those plans is destroyed.
+static std::mutex g_group_mu;
+static std::map<std::vector<const pscl_plan*>, pscl_group*> g_groups;
+extern "C" void pscl_group_destroy(pscl_group* g);
+static void drop_cached_groups(const pscl_plan* p) {
+    std::vector<pscl_group*> dead;
+    {
+        std::lock_guard<std::mutex> lk(g_group_mu);
+        for (auto it = g_groups.begin(); it != g_groups.end();) {
+            if (std::find(it->first.begin(), it->first.end(), p) != it->first.end()) {
+                dead.push_back(it->second);
+                it = g_groups.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (pscl_group* g : dead) pscl_group_destroy(g);
+}
+
 static void default_launch(int dtype, int& threads, int& budget) {
     threads = dtype == PSCL_F32 ? 128 : 64;
     budget = dtype == PSCL_F32 ? 20 * 1024 : (dtype == PSCL_I16 ? 10 * 1024 : 12 * 1024);
@@ -1499,6 +1612,7 @@ pscl_status pscl_schedule(int N, const uint8_t* frozen_mask, int L, int spc_max,
 
 void pscl_plan_destroy(pscl_plan* p) {
     if (!p) return;
+    drop_cached_groups(p);
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
@@ -1774,6 +1888,200 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     if (st == PSCL_OK && best_t < 0.f) st = PSCL_E_UNSUPPORTED;
     if (st == PSCL_OK && best_ms) *best_ms = best_t;
     return st;
+}
+
+void pscl_group_destroy(pscl_group* g) {
+    if (!g) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != g->device) (void)hipSetDevice(g->device);
+    for (int i = 0; i < pscl_group::SLOTS; ++i)
+        if (g->ev[i]) (void)hipEventSynchronize(g->ev[i]);
+    for (int i = 0; i < pscl_group::SLOTS; ++i) {
+        if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+        (void)hipFree(g->d_jobs[i]);
+        (void)hipFree(g->d_counter[i]);
+        if (g->h_jobs[i]) (void)hipHostFree(g->h_jobs[i]);
+    }
+    (void)hipFree(g->d_sched);
+    (void)hipFree(g->d_plans);
+    for (int i = 0; i < pscl_group::SLOTS; ++i) (void)hipFree(g->d_ws[i]);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    delete g;
+}
+
+pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int max_jobs,
+                              const pscl_launch_cfg* cfg, pscl_group** out) {
+    if (!out || !plans || n_plans < 1 || max_jobs < 1) return PSCL_E_INVALID;
+    for (int i = 0; i < n_plans; ++i) {
+        if (!plans[i]) return PSCL_E_INVALID;
+        if (plans[i]->dtype != plans[0]->dtype || plans[i]->device != plans[0]->device)
+            return PSCL_E_UNSUPPORTED;
+    }
+    const int dtype = plans[0]->dtype;
+    int NT = 0, budget = 0;
+    default_launch(dtype, NT, budget);
+    if (cfg && cfg->threads) NT = cfg->threads;
+    if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
+    if (dev != plans[0]->device) return PSCL_E_INVALID;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return PSCL_E_NODEV;
+
+    pscl_group* g = new pscl_group();
+    g->device = dev;
+    g->dtype = dtype;
+    g->NT = NT;
+    g->max_jobs = max_jobs;
+    int64_t n_rec = 0;
+    for (int i = 0; i < n_plans; ++i) {
+        const pscl_plan* p = plans[i];
+        g->plans.push_back(p);
+        g->cost.push_back((double)p->N * p->n * p->L);
+        g->lds_bytes = std::max(g->lds_bytes, p->lds_bytes);
+        g->ws_frame = std::max<int64_t>(g->ws_frame, p->args.ws_frame);
+        n_rec += p->args.n_ops;
+    }
+    const void* kern = dtype == PSCL_F32   ? (const void*)&decode_mixed_kernel<float>
+                       : dtype == PSCL_I16 ? (const void*)&decode_mixed_kernel<int16_t>
+                                           : (const void*)&decode_mixed_kernel<int8_t>;
+    pscl_status st = hip_status(
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, g->lds_bytes));
+    int occ = 0;
+    if (st == PSCL_OK)
+        st = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, g->lds_bytes));
+    if (st == PSCL_OK && occ < 1) st = PSCL_E_UNSUPPORTED;
+    g->grid = occ * prop.multiProcessorCount;
+    // concatenated schedules and the per-plan argument table
+    std::vector<DevPlan> dp(n_plans);
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&g->d_sched, (size_t)n_rec * 8));
+    int64_t base = 0;
+    for (int i = 0; i < n_plans && st == PSCL_OK; ++i) {
+        const pscl_plan* p = plans[i];
+        st = hip_status(hipMemcpy(g->d_sched + base, p->d_ops, (size_t)p->args.n_ops * 8,
+                                  hipMemcpyDeviceToDevice));
+        dp[i].a = p->args;
+        dp[i].a.ws = nullptr;
+        dp[i].op_base = base;
+        base += p->args.n_ops;
+    }
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&g->d_plans, sizeof(DevPlan) * n_plans));
+    if (st == PSCL_OK)
+        st = hip_status(hipMemcpy(g->d_plans, dp.data(), sizeof(DevPlan) * n_plans,
+                                  hipMemcpyHostToDevice));
+    for (int i = 0; i < pscl_group::SLOTS && st == PSCL_OK; ++i) {
+        if (g->ws_frame > 0)
+            st = hip_status(hipMalloc((void**)&g->d_ws[i], (size_t)(g->ws_frame * g->grid)));
+        if (st != PSCL_OK) break;
+        st = hip_status(hipMalloc((void**)&g->d_jobs[i], sizeof(DevJob) * max_jobs));
+        if (st == PSCL_OK)
+            st = hip_status(hipHostMalloc((void**)&g->h_jobs[i], sizeof(DevJob) * max_jobs));
+        if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&g->d_counter[i], 8));
+        if (st == PSCL_OK) st = hip_status(hipEventCreateWithFlags(&g->ev[i], hipEventDisableTiming));
+    }
+    if (st != PSCL_OK) {
+        pscl_group_destroy(g);
+        return st;
+    }
+    *out = g;
+    return PSCL_OK;
+}
+
+pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, void* stream) {
+    if (!g || n_jobs < 0 || (n_jobs > 0 && !jobs)) return PSCL_E_INVALID;
+    std::vector<int> idx;
+    int64_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        const pscl_job& J = jobs[j];
+        if (J.plan < 0 || J.plan >= (int)g->plans.size() || J.F < 0) return PSCL_E_INVALID;
+        if (J.F == 0) continue;
+        if (!J.llr || !J.u_hat || ((uintptr_t)J.llr & 15u) != 0) return PSCL_E_INVALID;
+        idx.push_back(j);
+        total += J.F;
+    }
+    if (idx.empty()) return PSCL_OK;
+    if ((int)idx.size() > g->max_jobs) return PSCL_E_INVALID;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return PSCL_E_HIP;
+    // most expensive frames first, so that the cheap ones fill the tail
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        return g->cost[jobs[x].plan] > g->cost[jobs[y].plan];
+    });
+    std::lock_guard<std::mutex> lk(g->mu);
+    const int slot = g->next_slot;
+    g->next_slot = (slot + 1) % pscl_group::SLOTS;
+    // the slot's previous launch must be done with its job table
+    if (g->used[slot] && hipEventSynchronize(g->ev[slot]) != hipSuccess) return PSCL_E_HIP;
+    DevJob* h = g->h_jobs[slot];
+    int64_t base = 0;
+    for (size_t i = 0; i < idx.size(); ++i) {
+        const pscl_job& J = jobs[idx[i]];
+        h[i].llr = J.llr;
+        h[i].u_hat = J.u_hat;
+        h[i].crc_ok = J.crc_ok;
+        h[i].pm = J.pm;
+        h[i].F = J.F;
+        h[i].base = base;
+        h[i].plan = J.plan;
+        h[i].pad = 0;
+        base += J.F;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    e = hipMemcpyAsync(g->d_jobs[slot], h, sizeof(DevJob) * idx.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_status(e);
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, g->d_counter[slot]);
+    const int grid = (int)std::min<int64_t>(total, g->grid);
+    const int nj = (int)idx.size();
+    switch (g->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL(decode_mixed_kernel<float>, dim3(grid), dim3(g->NT), g->lds_bytes, s,
+                               g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
+                               g->ws_frame, g->d_counter[slot]);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL(decode_mixed_kernel<int16_t>, dim3(grid), dim3(g->NT), g->lds_bytes,
+                               s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
+                               g->ws_frame, g->d_counter[slot]);
+            break;
+        default:
+            hipLaunchKernelGGL(decode_mixed_kernel<int8_t>, dim3(grid), dim3(g->NT), g->lds_bytes,
+                               s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
+                               g->ws_frame, g->d_counter[slot]);
+            break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return PSCL_E_HIP;
+    e = hipEventRecord(g->ev[slot], s);
+    if (e != hipSuccess) return PSCL_E_HIP;
+    g->used[slot] = true;
+    return PSCL_OK;
+}
+
+pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
+                              int n_jobs, void* stream) {
+    if (!plans || n_plans < 1 || n_jobs < 0 || (n_jobs > 0 && !jobs)) return PSCL_E_INVALID;
+    std::vector<const pscl_plan*> key(plans, plans + n_plans);
+    for (const pscl_plan* p : key)
+        if (!p) return PSCL_E_INVALID;
+    pscl_group* g = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_group_mu);
+        auto it = g_groups.find(key);
+        if (it != g_groups.end() && it->second->max_jobs >= n_jobs) g = it->second;
+    }
+    if (!g) {
+        pscl_status st = pscl_group_create(plans, n_plans, std::max(64, n_jobs), nullptr, &g);
+        if (st != PSCL_OK) return st;
+        pscl_group* old = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_group_mu);
+            auto it = g_groups.find(key);
+            if (it != g_groups.end()) old = it->second;
+            g_groups[key] = g;
+        }
+        if (old) pscl_group_destroy(old);
+    }
+    return pscl_group_decode(g, jobs, n_jobs, stream);
 }
 
 }  // extern "C"

@@ -160,3 +160,19 @@ def test_launch_cfg_and_autotune_validate_arguments(pk):
     assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, None, None) == 1
     assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, ctypes.byref(best),
                                 None) == 1
+
+
+def test_mixed_launch_validates_arguments(pk):
+    h = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    # no plans, bad job bound
+    assert pk.lib.pscl_group_create(None, 1, 8, None, ctypes.byref(h)) == 1
+    plans = (vp * 1)(None)
+    assert pk.lib.pscl_group_create(plans, 1, 8, None, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_group_create(plans, 0, 8, None, ctypes.byref(h)) == 1
+    assert not h.value
+    assert pk.lib.pscl_group_decode(None, None, 0, None) == 1
+    assert pk.lib.pscl_decode_mixed(None, 1, None, 0, None) == 1
+    assert pk.lib.pscl_decode_mixed(plans, 1, None, 0, None) == 1
+    assert pk.lib.pscl_decode_mixed(plans, 1, None, -1, None) == 1
+    pk.lib.pscl_group_destroy(None)
