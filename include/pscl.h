@@ -55,7 +55,8 @@ typedef enum {
     PSCL_E_UNSUPPORTED = 2, /* valid, but no kernel for this combination */
     PSCL_E_NOMEM = 3,       /* device allocation failed */
     PSCL_E_HIP = 4,         /* HIP runtime error */
-    PSCL_E_NODEV = 5        /* no usable gfx950 device */
+    PSCL_E_NODEV = 5,       /* no usable gfx950 device */
+    PSCL_E_BUSY = 6         /* a server holds as many requests as it admits */
 } pscl_status;
 
 typedef enum { PSCL_F32 = 0, PSCL_I16 = 1, PSCL_I8 = 2 } pscl_dtype;
@@ -208,22 +209,25 @@ typedef struct pscl_group pscl_group;
  * A group of plans decoded together.  All plans must have one dtype and
  * belong to the current device (PSCL_E_UNSUPPORTED / PSCL_E_INVALID
  * otherwise) and must outlive the group.  max_jobs bounds the non-empty
- * jobs of one call.  cfg (NULL allowed) sets the threads per workgroup;
+ * jobs of one call; max_inflight (1..8) the calls in flight at once (4 for
+ * the group pscl_decode_mixed keeps).  cfg (NULL allowed) sets the threads
+ * per workgroup;
  * each plan keeps its own LDS layout, and the launch reserves the largest.
  * Allocates the concatenated schedules and, per call in flight, a workspace
  * for the largest plan and a pinned job table, so pscl_group_decode never
  * allocates.
  */
 pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int max_jobs,
-                              const pscl_launch_cfg* cfg, pscl_group** out);
+                              int max_inflight, const pscl_launch_cfg* cfg, pscl_group** out);
 
 /* Release a group (NULL allowed) after its launches have finished. */
 void pscl_group_destroy(pscl_group* group);
 
 /*
- * Decode the jobs in one launch on the stream (asynchronous).  Up to four
- * calls may be in flight per group, on any streams (each has its own job
- * table and workspace); a fifth waits on the host for the first to finish.  Returns PSCL_E_INVALID for a bad plan index, F < 0,
+ * Decode the jobs in one launch on the stream (asynchronous).  Up to
+ * max_inflight calls may be in flight per group, on any streams (each has
+ * its own job table and workspace, taken in turn); a further call waits on
+ * the host for the oldest to finish.  Returns PSCL_E_INVALID for a bad plan index, F < 0,
  * null or misaligned required pointers, or more than max_jobs non-empty
  * jobs.  Results are identical to pscl_decode of each job with its plan.
  */
@@ -236,6 +240,75 @@ pscl_status pscl_group_decode(pscl_group* group, const pscl_job* jobs, int n_job
  */
 pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
                               int n_jobs, void* stream);
+
+/*
+ * Serving.  A server decodes requests (one pscl_job each: F frames of one
+ * of its codes, in the caller's device buffers) as they arrive.  A
+ * dispatcher thread keeps up to `streams` launches in flight, one per
+ * stream; whenever a stream is free it launches every pending request (up
+ * to the batch limits) as one mixed launch, so requests that arrive while
+ * others run join the next launch as soon as a stream frees up (continuous
+ * batching), and launches on different streams overlap on the device.
+ * Each request's results equal pscl_decode of it alone.  Latency runs from
+ * submission (or, in pscl_replay, the scheduled arrival) to the moment the
+ * dispatcher sees the launch that decoded it complete.
+ */
+typedef struct pscl_server pscl_server;
+
+typedef struct {
+    const pscl_plan* const* plans; /* the codes served, one dtype; they must outlive the server */
+    int n_plans;
+    int streams;                /* launches in flight, 1..8 (0 = 2) */
+    int max_requests;           /* requests held, queued or running (0 = 4096) */
+    int64_t max_pending_frames; /* frames queued and not yet launched (0 = no limit) */
+    int64_t max_batch_frames;   /* frames per launch (0 = no limit; one request at least) */
+    int max_batch_requests;     /* requests per launch (0 = 1024) */
+} pscl_server_cfg;
+
+/* Create a server on the current device (allocates one group, stream and
+ * event per stream, and starts the dispatcher thread). */
+pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out);
+
+/* Finish every held request, stop the dispatcher and release the server
+ * (NULL allowed). */
+void pscl_server_destroy(pscl_server* server);
+
+/*
+ * Queue one request and return its ticket.  The job's buffers stay the
+ * caller's and must stay valid until the request is done.  PSCL_E_BUSY when
+ * the server already holds max_requests requests or the request would take
+ * the queued frames beyond max_pending_frames (admission control: the
+ * caller retries later); PSCL_E_INVALID for a bad job or one larger than
+ * max_pending_frames.  A failed launch is reported by every later call.
+ */
+pscl_status pscl_server_submit(pscl_server* server, const pscl_job* job, uint64_t* ticket);
+
+/* *done = 1 once the request's outputs are complete in device memory (and
+ * its latency in microseconds to *latency_us when not NULL); a ticket is
+ * forgotten once reported done. */
+pscl_status pscl_server_poll(pscl_server* server, uint64_t ticket, int* done,
+                             double* latency_us);
+
+/* Block until the request is done (then as pscl_server_poll). */
+pscl_status pscl_server_wait(pscl_server* server, uint64_t ticket, double* latency_us);
+
+/* Requests, frames and launches completed, and the 50th / 99th percentile
+ * latencies (microseconds) of those requests; reset != 0 clears them. */
+pscl_status pscl_server_stats(pscl_server* server, int64_t* requests, int64_t* frames,
+                              int64_t* launches, double* p50_us, double* p99_us, int reset);
+
+/*
+ * Replay a request trace: job i arrives arrival_us[i] microseconds after
+ * the start (non-decreasing; the host clock is busy-waited).  Through
+ * `server`, or, when server is NULL, as the plain baseline of one
+ * pscl_decode per request with plans[job.plan], issued in arrival order on
+ * `stream`.  Blocks until every request is done and writes each request's
+ * latency (from its scheduled arrival, so queueing counts) and the elapsed
+ * time from the start to the last completion.
+ */
+pscl_status pscl_replay(pscl_server* server, const pscl_plan* const* plans, int n_plans,
+                        const pscl_job* jobs, const double* arrival_us, int n, void* stream,
+                        double* latency_us, double* elapsed_us);
 
 /* Launch shape chosen for a plan: frames per workgroup, threads per
  * workgroup, workgroups, LDS bytes per workgroup, bytes of global workspace,

@@ -16,9 +16,12 @@ from ._binding import (  # noqa: F401
     OP_NAMES,
     Plan,
     PsclError,
+    Server,
+    ServerCfg,
     autotune,
     decode,
     decode_mixed,
     lib,
+    replay,
     schedule,
 )

@@ -28,6 +28,7 @@ _STATUS = {
     3: "device out of memory",
     4: "HIP runtime error",
     5: "no gfx950 device",
+    6: "busy",
 }
 
 
@@ -48,6 +49,15 @@ class Job(ctypes.Structure):
 
     _fields_ = [("plan", ctypes.c_int), ("llr", ctypes.c_void_p), ("F", ctypes.c_int64),
                 ("u_hat", ctypes.c_void_p), ("crc_ok", ctypes.c_void_p), ("pm", ctypes.c_void_p)]
+
+
+class ServerCfg(ctypes.Structure):
+    """pscl_server_cfg (zero fields take the defaults)."""
+
+    _fields_ = [("plans", ctypes.POINTER(ctypes.c_void_p)), ("n_plans", ctypes.c_int),
+                ("streams", ctypes.c_int), ("max_requests", ctypes.c_int),
+                ("max_pending_frames", ctypes.c_int64), ("max_batch_frames", ctypes.c_int64),
+                ("max_batch_requests", ctypes.c_int)]
 
 
 def _load():
@@ -86,8 +96,8 @@ def _load():
                                   vp, c_i64, vp, ctypes.POINTER(LaunchCfg),
                                   ctypes.POINTER(ctypes.c_float)]
     lib.pscl_autotune.restype = c_int
-    lib.pscl_group_create.argtypes = [ctypes.POINTER(vp), c_int, c_int, ctypes.POINTER(LaunchCfg),
-                                      ctypes.POINTER(vp)]
+    lib.pscl_group_create.argtypes = [ctypes.POINTER(vp), c_int, c_int, c_int,
+                                      ctypes.POINTER(LaunchCfg), ctypes.POINTER(vp)]
     lib.pscl_group_create.restype = c_int
     lib.pscl_group_destroy.argtypes = [vp]
     lib.pscl_group_destroy.restype = None
@@ -95,6 +105,23 @@ def _load():
     lib.pscl_group_decode.restype = c_int
     lib.pscl_decode_mixed.argtypes = [ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), c_int, vp]
     lib.pscl_decode_mixed.restype = c_int
+    lib.pscl_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+    lib.pscl_server_create.restype = c_int
+    lib.pscl_server_destroy.argtypes = [vp]
+    lib.pscl_server_destroy.restype = None
+    lib.pscl_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(c_u64)]
+    lib.pscl_server_submit.restype = c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.pscl_server_poll.argtypes = [vp, c_u64, ip, dp]
+    lib.pscl_server_poll.restype = c_int
+    lib.pscl_server_wait.argtypes = [vp, c_u64, dp]
+    lib.pscl_server_wait.restype = c_int
+    i64p = ctypes.POINTER(c_i64)
+    lib.pscl_server_stats.argtypes = [vp, i64p, i64p, i64p, dp, dp, c_int]
+    lib.pscl_server_stats.restype = c_int
+    lib.pscl_replay.argtypes = [vp, ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), dp, c_int, vp,
+                                dp, dp]
+    lib.pscl_replay.restype = c_int
     return lib
 
 
@@ -255,13 +282,13 @@ class Group:
     """A group of plans of one dtype decoded together in one persistent
     launch (see pscl_group_create); the plans must outlive it."""
 
-    def __init__(self, plans, max_jobs: int = 64, threads: int = 0):
+    def __init__(self, plans, max_jobs: int = 64, max_inflight: int = 4, threads: int = 0):
         self.plans = list(plans)
         hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         cfg = LaunchCfg(threads, 0)
         h = ctypes.c_void_p(None)
-        _check(lib.pscl_group_create(hs, len(self.plans), max_jobs, ctypes.byref(cfg),
-                                     ctypes.byref(h)), "pscl_group_create")
+        _check(lib.pscl_group_create(hs, len(self.plans), max_jobs, max_inflight,
+                                     ctypes.byref(cfg), ctypes.byref(h)), "pscl_group_create")
         self._h = h
 
     def decode(self, work):
@@ -293,3 +320,90 @@ def decode_mixed(plans, work):
     _check(lib.pscl_decode_mixed(hs, len(plans), arr, len(work), _stream_handle(plans[0].device)),
            "pscl_decode_mixed")
     return outs
+
+
+class Server:
+    """A serving loop over a list of plans of one dtype (see
+    pscl_server_create).  submit() keeps each request's buffers alive until
+    it has been reported done."""
+
+    def __init__(self, plans, streams: int = 2, max_requests: int = 0,
+                 max_pending_frames: int = 0, max_batch_frames: int = 0,
+                 max_batch_requests: int = 0):
+        self.plans = list(plans)
+        self._hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        cfg = ServerCfg(self._hs, len(self.plans), streams, max_requests, max_pending_frames,
+                        max_batch_frames, max_batch_requests)
+        h = ctypes.c_void_p(None)
+        _check(lib.pscl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pscl_server_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, plan_index: int, llr):
+        """Queue F frames (llr F x N device tensor) of plans[plan_index];
+        returns (ticket, (u_hat, crc_ok, pm)).  Raises PsclError (status 6)
+        when the server is full."""
+        arr, outs = _jobs(self.plans, [(plan_index, llr)])
+        t = ctypes.c_uint64(0)
+        _check(lib.pscl_server_submit(self._h, arr, ctypes.byref(t)), "pscl_server_submit")
+        self._live[t.value] = (llr, outs[0])
+        return t.value, outs[0]
+
+    def poll(self, ticket: int):
+        """(done, latency in microseconds or None)."""
+        d = ctypes.c_int(0)
+        lat = ctypes.c_double(0.0)
+        _check(lib.pscl_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(lat)),
+               "pscl_server_poll")
+        if d.value:
+            self._live.pop(ticket, None)
+            return True, lat.value
+        return False, None
+
+    def wait(self, ticket: int) -> float:
+        lat = ctypes.c_double(0.0)
+        _check(lib.pscl_server_wait(self._h, ticket, ctypes.byref(lat)), "pscl_server_wait")
+        self._live.pop(ticket, None)
+        return lat.value
+
+    def stats(self, reset: bool = False) -> dict:
+        r, f, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        p50, p99 = ctypes.c_double(), ctypes.c_double()
+        _check(lib.pscl_server_stats(self._h, ctypes.byref(r), ctypes.byref(f), ctypes.byref(n),
+                                     ctypes.byref(p50), ctypes.byref(p99), int(reset)),
+               "pscl_server_stats")
+        return {"requests": r.value, "frames": f.value, "launches": n.value,
+                "p50_us": p50.value, "p99_us": p99.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pscl_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def replay(plans, work, arrival_us, server=None):
+    """pscl_replay: request i = work[i] = (plan index, llr tensor) arrives
+    arrival_us[i] microseconds after the start; through `server`, or as one
+    pscl_decode per request when server is None.  Returns (outputs,
+    latencies in microseconds as a numpy array, elapsed microseconds)."""
+    plans = list(plans)
+    hs = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    arr, outs = _jobs(plans, work)
+    arrivals = np.ascontiguousarray(np.asarray(arrival_us, dtype=np.float64))
+    if arrivals.shape != (len(work),):
+        raise ValueError("one arrival time per request")
+    lat = np.zeros(len(work), dtype=np.float64)
+    el = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.pscl_replay(server._h if server is not None else None, hs, len(plans), arr,
+                           arrivals.ctypes.data_as(dp), len(work),
+                           _stream_handle(plans[0].device), lat.ctypes.data_as(dp),
+                           ctypes.byref(el)), "pscl_replay")
+    return outs, lat, el.value

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libpscl.so")
-SOURCES = [os.path.join(CSRC, "decoder.hip"), os.path.join(CSRC, "schedule.cpp")]
+SOURCES = [os.path.join(CSRC, "decoder.hip"), os.path.join(CSRC, "schedule.cpp"),
+           os.path.join(CSRC, "server.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

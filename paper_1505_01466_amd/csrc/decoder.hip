@@ -1410,19 +1410,20 @@ struct pscl_plan {
 };
 
 struct pscl_group {
-    static constexpr int SLOTS = 4;  // job tables in flight
     int device = 0, dtype = 0, NT = 64, lds_bytes = 0, grid = 0, max_jobs = 0;
+    int slots = 0;  // calls in flight
     int64_t ws_frame = 0;
     std::vector<const pscl_plan*> plans;
     std::vector<double> cost;  // relative work per frame, for ordering jobs
     uint64_t* d_sched = nullptr;
     DevPlan* d_plans = nullptr;
-    uint8_t* d_ws[SLOTS] = {};  // one workspace per call in flight
-    DevJob* d_jobs[SLOTS] = {};
-    DevJob* h_jobs[SLOTS] = {};  // pinned staging
-    unsigned long long* d_counter[SLOTS] = {};
-    hipEvent_t ev[SLOTS] = {};
-    bool used[SLOTS] = {};
+    // per call in flight: workspace, job table (device and pinned staging),
+    // frame counter, completion event
+    std::vector<uint8_t*> d_ws;
+    std::vector<DevJob*> d_jobs, h_jobs;
+    std::vector<unsigned long long*> d_counter;
+    std::vector<hipEvent_t> ev;
+    std::vector<char> used;
     int next_slot = 0;
     std::mutex mu;
 };
@@ -1588,6 +1589,8 @@ const char* pscl_status_str(pscl_status s) {
             return "HIP runtime error";
         case PSCL_E_NODEV:
             return "no gfx950 device";
+        case PSCL_E_BUSY:
+            return "busy: the server holds as many requests as it admits";
     }
     return "unknown status";
 }
@@ -1894,24 +1897,25 @@ void pscl_group_destroy(pscl_group* g) {
     if (!g) return;
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != g->device) (void)hipSetDevice(g->device);
-    for (int i = 0; i < pscl_group::SLOTS; ++i)
+    for (int i = 0; i < g->slots; ++i)
         if (g->ev[i]) (void)hipEventSynchronize(g->ev[i]);
-    for (int i = 0; i < pscl_group::SLOTS; ++i) {
+    for (int i = 0; i < g->slots; ++i) {
         if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
         (void)hipFree(g->d_jobs[i]);
         (void)hipFree(g->d_counter[i]);
+        (void)hipFree(g->d_ws[i]);
         if (g->h_jobs[i]) (void)hipHostFree(g->h_jobs[i]);
     }
     (void)hipFree(g->d_sched);
     (void)hipFree(g->d_plans);
-    for (int i = 0; i < pscl_group::SLOTS; ++i) (void)hipFree(g->d_ws[i]);
     if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
 }
 
 pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int max_jobs,
-                              const pscl_launch_cfg* cfg, pscl_group** out) {
+                              int max_inflight, const pscl_launch_cfg* cfg, pscl_group** out) {
     if (!out || !plans || n_plans < 1 || max_jobs < 1) return PSCL_E_INVALID;
+    if (max_inflight < 1 || max_inflight > 8) return PSCL_E_INVALID;
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return PSCL_E_INVALID;
         if (plans[i]->dtype != plans[0]->dtype || plans[i]->device != plans[0]->device)
@@ -1933,6 +1937,13 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
     g->dtype = dtype;
     g->NT = NT;
     g->max_jobs = max_jobs;
+    g->slots = max_inflight;
+    g->d_ws.assign(max_inflight, nullptr);
+    g->d_jobs.assign(max_inflight, nullptr);
+    g->h_jobs.assign(max_inflight, nullptr);
+    g->d_counter.assign(max_inflight, nullptr);
+    g->ev.assign(max_inflight, nullptr);
+    g->used.assign(max_inflight, 0);
     int64_t n_rec = 0;
     for (int i = 0; i < n_plans; ++i) {
         const pscl_plan* p = plans[i];
@@ -1969,7 +1980,7 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
     if (st == PSCL_OK)
         st = hip_status(hipMemcpy(g->d_plans, dp.data(), sizeof(DevPlan) * n_plans,
                                   hipMemcpyHostToDevice));
-    for (int i = 0; i < pscl_group::SLOTS && st == PSCL_OK; ++i) {
+    for (int i = 0; i < max_inflight && st == PSCL_OK; ++i) {
         if (g->ws_frame > 0)
             st = hip_status(hipMalloc((void**)&g->d_ws[i], (size_t)(g->ws_frame * g->grid)));
         if (st != PSCL_OK) break;
@@ -2009,7 +2020,7 @@ pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, v
     });
     std::lock_guard<std::mutex> lk(g->mu);
     const int slot = g->next_slot;
-    g->next_slot = (slot + 1) % pscl_group::SLOTS;
+    g->next_slot = (slot + 1) % g->slots;
     // the slot's previous launch must be done with its job table
     if (g->used[slot] && hipEventSynchronize(g->ev[slot]) != hipSuccess) return PSCL_E_HIP;
     DevJob* h = g->h_jobs[slot];
@@ -2053,7 +2064,7 @@ pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, v
     if (e != hipSuccess) return PSCL_E_HIP;
     e = hipEventRecord(g->ev[slot], s);
     if (e != hipSuccess) return PSCL_E_HIP;
-    g->used[slot] = true;
+    g->used[slot] = 1;
     return PSCL_OK;
 }
 
@@ -2070,7 +2081,7 @@ pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const 
         if (it != g_groups.end() && it->second->max_jobs >= n_jobs) g = it->second;
     }
     if (!g) {
-        pscl_status st = pscl_group_create(plans, n_plans, std::max(64, n_jobs), nullptr, &g);
+        pscl_status st = pscl_group_create(plans, n_plans, std::max(64, n_jobs), 4, nullptr, &g);
         if (st != PSCL_OK) return st;
         pscl_group* old = nullptr;
         {

@@ -1,0 +1,391 @@
+// Serving loop: requests (one pscl_job each) decoded as they arrive, by a
+// dispatcher thread that keeps up to S mixed launches in flight, one per
+// stream, and whenever a stream is free launches every pending request as
+// one batch (continuous batching).  Built on the public group API; each
+// stream owns a group with one call in flight, so no two launches share a
+// workspace.  A replay driver submits a request trace at given arrival times
+// through a server, or as plain per-request pscl_decode launches (the
+// baseline), and reports per-request latencies.
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "pscl.h"
+
+namespace {
+
+double now_us() {
+    using namespace std::chrono;
+    return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() *
+           1e-3;
+}
+
+struct Req {
+    pscl_job job;
+    uint64_t ticket;
+    double t_arrive;  // latency reference
+    double* sink;     // if set, the latency goes here and the ticket is not kept
+};
+
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    const size_t k = std::min(v.size() - 1, (size_t)(q * (double)(v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + (ptrdiff_t)k, v.end());
+    return v[k];
+}
+
+}  // namespace
+
+struct pscl_server {
+    int device = 0;
+    int S = 2;
+    int max_requests = 4096, max_batch_requests = 1024;
+    int64_t max_pending_frames = 0, max_batch_frames = 0;
+    std::vector<const pscl_plan*> plans;
+    std::vector<pscl_group*> groups;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> ev;
+    std::vector<std::vector<Req>> inflight;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req> pending;
+    int64_t pending_frames = 0;
+    int64_t held = 0;  // pending + in flight
+    std::unordered_map<uint64_t, double> done;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    pscl_status error = PSCL_OK;  // first launch failure, reported by later calls
+
+    std::vector<double> lat;
+    int64_t n_req = 0, n_frames = 0, n_launch = 0;
+    std::thread th;
+
+    void run();
+    pscl_status submit(const pscl_job& job, double t_arrive, double* sink, uint64_t* ticket);
+};
+
+void pscl_server::run() {
+    (void)hipSetDevice(device);
+    std::vector<pscl_job> jobs;
+    for (;;) {
+        bool progress = false;
+        // completions
+        for (int s = 0; s < S; ++s) {
+            if (inflight[s].empty()) continue;
+            const hipError_t q = hipEventQuery(ev[s]);
+            if (q == hipErrorNotReady) continue;
+            const double t = now_us();
+            std::lock_guard<std::mutex> lk(mu);
+            if (q != hipSuccess && error == PSCL_OK) error = PSCL_E_HIP;
+            for (const Req& r : inflight[s]) {
+                const double l = t - r.t_arrive;
+                if (r.sink) *r.sink = l;
+                else done[r.ticket] = l;
+                lat.push_back(l);
+                n_req += 1;
+                n_frames += r.job.F;
+                held -= 1;
+            }
+            inflight[s].clear();
+            progress = true;
+            cv_done.notify_all();
+        }
+        // launches: every free stream takes what is pending
+        for (int s = 0; s < S; ++s) {
+            if (!inflight[s].empty()) continue;
+            std::vector<Req>& batch = inflight[s];
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                int64_t fr = 0;
+                while (!pending.empty() && (int)batch.size() < max_batch_requests) {
+                    const Req& r = pending.front();
+                    if (!batch.empty() && max_batch_frames > 0 && fr + r.job.F > max_batch_frames)
+                        break;
+                    fr += r.job.F;
+                    pending_frames -= r.job.F;
+                    batch.push_back(r);
+                    pending.pop_front();
+                }
+            }
+            if (batch.empty()) continue;
+            jobs.clear();
+            for (const Req& r : batch) jobs.push_back(r.job);
+            pscl_status st = pscl_group_decode(groups[s], jobs.data(), (int)jobs.size(), streams[s]);
+            if (st == PSCL_OK && hipEventRecord(ev[s], streams[s]) != hipSuccess) st = PSCL_E_HIP;
+            if (st != PSCL_OK) {
+                // the requests complete as failed; later calls report it
+                std::lock_guard<std::mutex> lk(mu);
+                if (error == PSCL_OK) error = st;
+                (void)hipStreamSynchronize(streams[s]);
+                (void)hipEventRecord(ev[s], streams[s]);
+            }
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                n_launch += 1;
+            }
+            progress = true;
+        }
+        if (progress) continue;
+        std::unique_lock<std::mutex> lk(mu);
+        bool busy = false;
+        for (int s = 0; s < S; ++s) busy = busy || !inflight[s].empty();
+        if (!busy && pending.empty()) {
+            if (stop) return;
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        } else {
+            lk.unlock();
+            std::this_thread::yield();
+        }
+    }
+}
+
+pscl_status pscl_server::submit(const pscl_job& job, double t_arrive, double* sink,
+                                 uint64_t* ticket) {
+    if (job.plan < 0 || job.plan >= (int)plans.size() || job.F < 0) return PSCL_E_INVALID;
+    if (job.F > 0 && (!job.llr || !job.u_hat || ((uintptr_t)job.llr & 15u) != 0))
+        return PSCL_E_INVALID;
+    if (max_pending_frames > 0 && job.F > max_pending_frames) return PSCL_E_INVALID;  // never fits
+    std::lock_guard<std::mutex> lk(mu);
+    if (error != PSCL_OK) return error;
+    if (held >= max_requests) return PSCL_E_BUSY;
+    if (max_pending_frames > 0 && pending_frames + job.F > max_pending_frames) return PSCL_E_BUSY;
+    const uint64_t t = next_ticket++;
+    if (ticket) *ticket = t;
+    if (job.F == 0) {  // nothing to decode: done at once
+        if (sink) *sink = 0.0;
+        else done[t] = 0.0;
+        cv_done.notify_all();
+        return PSCL_OK;
+    }
+    pending.push_back(Req{job, t, t_arrive, sink});
+    pending_frames += job.F;
+    held += 1;
+    cv_work.notify_one();
+    return PSCL_OK;
+}
+
+extern "C" {
+
+void pscl_server_destroy(pscl_server* sv) {
+    if (!sv) return;
+    if (sv->th.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stop = true;
+        }
+        sv->cv_work.notify_all();
+        sv->th.join();
+    }
+    for (pscl_group* g : sv->groups) pscl_group_destroy(g);
+    for (hipEvent_t e : sv->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : sv->streams)
+        if (s) (void)hipStreamDestroy(s);
+    delete sv;
+}
+
+pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
+    if (!cfg || !out || !cfg->plans || cfg->n_plans < 1) return PSCL_E_INVALID;
+    if (cfg->streams < 0 || cfg->streams > 8 || cfg->max_requests < 0 ||
+        cfg->max_pending_frames < 0 || cfg->max_batch_frames < 0 || cfg->max_batch_requests < 0)
+        return PSCL_E_INVALID;
+    for (int i = 0; i < cfg->n_plans; ++i)
+        if (!cfg->plans[i]) return PSCL_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
+    pscl_server* sv = new pscl_server();
+    sv->device = dev;
+    sv->S = cfg->streams ? cfg->streams : 2;
+    if (cfg->max_requests) sv->max_requests = cfg->max_requests;
+    if (cfg->max_batch_requests) sv->max_batch_requests = cfg->max_batch_requests;
+    sv->max_pending_frames = cfg->max_pending_frames;
+    sv->max_batch_frames = cfg->max_batch_frames;
+    sv->plans.assign(cfg->plans, cfg->plans + cfg->n_plans);
+    sv->inflight.resize(sv->S);
+    pscl_status st = PSCL_OK;
+    for (int s = 0; s < sv->S && st == PSCL_OK; ++s) {
+        pscl_group* g = nullptr;
+        st = pscl_group_create(cfg->plans, cfg->n_plans, sv->max_batch_requests, 1, nullptr, &g);
+        if (st != PSCL_OK) break;
+        sv->groups.push_back(g);
+        hipStream_t str = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&str, hipStreamNonBlocking) != hipSuccess) st = PSCL_E_HIP;
+        sv->streams.push_back(str);
+        if (st == PSCL_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            st = PSCL_E_HIP;
+        sv->ev.push_back(e);
+    }
+    if (st != PSCL_OK) {
+        pscl_server_destroy(sv);
+        return st;
+    }
+    sv->th = std::thread([sv] { sv->run(); });
+    *out = sv;
+    return PSCL_OK;
+}
+
+pscl_status pscl_server_submit(pscl_server* sv, const pscl_job* job, uint64_t* ticket) {
+    if (!sv || !job) return PSCL_E_INVALID;
+    return sv->submit(*job, now_us(), nullptr, ticket);
+}
+
+pscl_status pscl_server_poll(pscl_server* sv, uint64_t ticket, int* is_done, double* latency_us) {
+    if (!sv || !is_done) return PSCL_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) {
+        if (ticket == 0 || ticket >= sv->next_ticket) return PSCL_E_INVALID;
+        *is_done = 0;
+        return sv->error;
+    }
+    *is_done = 1;
+    if (latency_us) *latency_us = it->second;
+    sv->done.erase(it);
+    return sv->error;
+}
+
+pscl_status pscl_server_wait(pscl_server* sv, uint64_t ticket, double* latency_us) {
+    if (!sv) return PSCL_E_INVALID;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (ticket == 0 || ticket >= sv->next_ticket) return PSCL_E_INVALID;
+    sv->cv_done.wait(lk, [&] { return sv->done.count(ticket) > 0 || sv->error != PSCL_OK; });
+    auto it = sv->done.find(ticket);
+    if (it == sv->done.end()) return sv->error;
+    if (latency_us) *latency_us = it->second;
+    sv->done.erase(it);
+    return sv->error;
+}
+
+pscl_status pscl_server_stats(pscl_server* sv, int64_t* requests, int64_t* frames,
+                              int64_t* launches, double* p50_us, double* p99_us, int reset) {
+    if (!sv) return PSCL_E_INVALID;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (requests) *requests = sv->n_req;
+    if (frames) *frames = sv->n_frames;
+    if (launches) *launches = sv->n_launch;
+    if (p50_us) *p50_us = percentile(sv->lat, 0.50);
+    if (p99_us) *p99_us = percentile(sv->lat, 0.99);
+    if (reset) {
+        sv->lat.clear();
+        sv->n_req = sv->n_frames = sv->n_launch = 0;
+    }
+    return sv->error;
+}
+
+pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_plans,
+                        const pscl_job* jobs, const double* arrival_us, int n, void* stream,
+                        double* latency_us, double* elapsed_us) {
+    if (n < 0 || (n > 0 && (!jobs || !arrival_us || !latency_us))) return PSCL_E_INVALID;
+    if (!sv && (!plans || n_plans < 1)) return PSCL_E_INVALID;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0 && arrival_us[i] < arrival_us[i - 1]) return PSCL_E_INVALID;
+        if (!sv && (jobs[i].plan < 0 || jobs[i].plan >= n_plans || !plans[jobs[i].plan]))
+            return PSCL_E_INVALID;
+    }
+    const double t0 = now_us();
+    if (sv) {
+        for (int i = 0; i < n; ++i) {
+            const double ta = t0 + arrival_us[i];
+            while (now_us() < ta) {
+            }
+            for (;;) {
+                const pscl_status st = sv->submit(jobs[i], ta, &latency_us[i], nullptr);
+                if (st == PSCL_OK) break;
+                if (st != PSCL_E_BUSY) return st;
+                std::this_thread::yield();
+            }
+        }
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->held == 0 || sv->error != PSCL_OK; });
+        if (elapsed_us) *elapsed_us = now_us() - t0;
+        return sv->error;
+    }
+    // baseline: one pscl_decode per request on one stream, in arrival
+    // order; completions (in order, one stream) observed by a poller
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
+    const int RING = 1024;
+    std::vector<hipEvent_t> evs(RING, nullptr);
+    pscl_status st = PSCL_OK;
+    for (int i = 0; i < RING && st == PSCL_OK; ++i)
+        if (hipEventCreateWithFlags(&evs[i], hipEventDisableTiming) != hipSuccess) st = PSCL_E_HIP;
+    std::mutex mu;
+    std::condition_variable cv;
+    int issued = 0, completed = 0;
+    bool failed = false;
+    std::vector<double> t_arr(n > 0 ? n : 1);
+    std::thread poller;
+    if (st == PSCL_OK) {
+        poller = std::thread([&] {
+            (void)hipSetDevice(dev);
+            for (;;) {
+                int head;
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return completed < issued || failed || completed == n; });
+                    if (completed == n || (failed && completed == issued)) return;
+                    head = completed;
+                }
+                hipError_t q;
+                while ((q = hipEventQuery(evs[head % RING])) == hipErrorNotReady) std::this_thread::yield();
+                const double t = now_us();
+                std::lock_guard<std::mutex> lk(mu);
+                latency_us[head] = t - t_arr[head];
+                if (q != hipSuccess) failed = true;
+                completed += 1;
+                cv.notify_all();
+            }
+        });
+    }
+    for (int i = 0; i < n && st == PSCL_OK; ++i) {
+        const double ta = t0 + arrival_us[i];
+        while (now_us() < ta) {
+        }
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return issued - completed < RING || failed; });
+            if (failed) {
+                st = PSCL_E_HIP;
+                break;
+            }
+        }
+        const pscl_job& J = jobs[i];
+        t_arr[i] = ta;
+        st = pscl_decode(plans[J.plan], J.llr, J.F, J.u_hat, J.crc_ok, J.pm, s);
+        if (st == PSCL_OK && hipEventRecord(evs[i % RING], s) != hipSuccess) st = PSCL_E_HIP;
+        std::lock_guard<std::mutex> lk(mu);
+        if (st != PSCL_OK) {
+            failed = true;
+        } else {
+            issued += 1;
+        }
+        cv.notify_all();
+    }
+    if (poller.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (st != PSCL_OK) failed = true;
+            cv.notify_all();
+        }
+        poller.join();
+    }
+    if (elapsed_us) *elapsed_us = now_us() - t0;
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    if (st == PSCL_OK && failed) st = PSCL_E_HIP;
+    return st;
+}
+
+}  // extern "C"

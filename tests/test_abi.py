@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(pk):
 
 
 def test_status_strings_and_version(pk):
-    for s in range(6):
+    for s in range(7):
         assert pk.lib.pscl_status_str(s)
     assert pk.lib.pscl_version() >= 100
 
@@ -166,13 +166,37 @@ def test_mixed_launch_validates_arguments(pk):
     h = ctypes.c_void_p()
     vp = ctypes.c_void_p
     # no plans, bad job bound
-    assert pk.lib.pscl_group_create(None, 1, 8, None, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_group_create(None, 1, 8, 4, None, ctypes.byref(h)) == 1
     plans = (vp * 1)(None)
-    assert pk.lib.pscl_group_create(plans, 1, 8, None, ctypes.byref(h)) == 1
-    assert pk.lib.pscl_group_create(plans, 0, 8, None, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_group_create(plans, 1, 8, 4, None, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_group_create(plans, 0, 8, 4, None, ctypes.byref(h)) == 1
     assert not h.value
     assert pk.lib.pscl_group_decode(None, None, 0, None) == 1
     assert pk.lib.pscl_decode_mixed(None, 1, None, 0, None) == 1
     assert pk.lib.pscl_decode_mixed(plans, 1, None, 0, None) == 1
     assert pk.lib.pscl_decode_mixed(plans, 1, None, -1, None) == 1
     pk.lib.pscl_group_destroy(None)
+
+
+def test_server_and_replay_validate_arguments(pk):
+    h = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    assert pk.lib.pscl_server_create(None, ctypes.byref(h)) == 1
+    plans = (vp * 1)(None)
+    for bad in (dict(n_plans=0), dict(n_plans=1), dict(n_plans=1, streams=9),
+                dict(n_plans=1, max_requests=-1)):
+        cfg = pk.ServerCfg(plans, bad.get("n_plans", 1), bad.get("streams", 0),
+                           bad.get("max_requests", 0), 0, 0, 0)
+        assert pk.lib.pscl_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert not h.value
+    t = ctypes.c_uint64()
+    d = ctypes.c_int()
+    assert pk.lib.pscl_server_submit(None, None, ctypes.byref(t)) == 1
+    assert pk.lib.pscl_server_poll(None, 1, ctypes.byref(d), None) == 1
+    assert pk.lib.pscl_server_wait(None, 1, None) == 1
+    assert pk.lib.pscl_server_stats(None, None, None, None, None, None, 0) == 1
+    pk.lib.pscl_server_destroy(None)
+    # replay: no plans for the baseline, negative count, missing arrays
+    assert pk.lib.pscl_replay(None, None, 0, None, None, 0, None, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, None, None, -1, None, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, None, None, 2, None, None, None) == 1

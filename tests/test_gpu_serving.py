@@ -1,0 +1,121 @@
+"""Serving: requests of mixed codes decoded as they arrive (pscl_server_*),
+and the replay driver (pscl_replay) through a server and as plain
+per-request launches.  Every request's result must equal decoding it alone
+with its plan (int8: bit for bit)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CODES = [
+    (256, 128, 8, synth.CRC8_POLY, 2.5, 2),
+    (512, 256, 8, synth.CRC8_POLY, 2.5, 8),
+    (1024, 860, 32, synth.CRC32_POLY, 4.0, 32),
+    (2048, 1723, 32, synth.CRC32_POLY, 4.0, 8),
+]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1505_01466_amd as pk
+
+    codes, plans = [], []
+    for N, K, r, poly, d, L in CODES:
+        code = synth.make_code(N, K, r, poly, d)
+        codes.append(code)
+        plans.append(pk.Plan(N, K, code.frozen, code.poly, r, L, "i8"))
+    return pk, torch, codes, plans
+
+
+def _requests(torch, codes, n, seed, fmax=64):
+    rng = np.random.default_rng(seed)
+    work = []
+    for i in range(n):
+        pi = int(rng.integers(len(codes)))
+        F = int(rng.integers(1, fmax + 1))
+        b = synth.make_batch(codes[pi], F, CODES[pi][4], (seed, i), "i8")
+        work.append((pi, torch.from_numpy(b.llr).cuda()))
+    return work
+
+
+def _alone(torch, plans, work):
+    out = [plans[pi].decode(llr) for pi, llr in work]
+    torch.cuda.synchronize()
+    return [[t.cpu().numpy() for t in o] for o in out]
+
+
+def _check(got, ref):
+    for i, (g, r) in enumerate(zip(got, ref)):
+        for a, b in zip(g, r):
+            assert (a.cpu().numpy() == b).all(), f"request {i}"
+
+
+def test_server_results_equal_alone(env):
+    pk, torch, codes, plans = env
+    work = _requests(torch, codes, 60, 5)
+    ref = _alone(torch, plans, work)
+    sv = pk.Server(plans, streams=2)
+    tickets = [sv.submit(pi, llr) for pi, llr in work]
+    lats = [sv.wait(t) for t, _ in tickets]
+    torch.cuda.synchronize()
+    _check([o for _, o in tickets], ref)
+    st = sv.stats()
+    _say(f"server: {st}")
+    assert st["requests"] == 60 and st["frames"] == sum(l.shape[0] for _, l in work)
+    assert 1 <= st["launches"] <= 60 and min(lats) > 0 and st["p99_us"] >= st["p50_us"] > 0
+    sv.close()
+
+
+@pytest.mark.parametrize("through_server", [True, False])
+def test_replay_poisson_arrivals(env, through_server):
+    pk, torch, codes, plans = env
+    n = 200
+    work = _requests(torch, codes, n, 11)
+    ref = _alone(torch, plans, work)
+    rng = np.random.default_rng(3)
+    arrivals = np.cumsum(rng.exponential(1e6 / 20000.0, n))  # 20k requests/s
+    sv = pk.Server(plans, streams=3) if through_server else None
+    outs, lat, elapsed = pk.replay(plans, work, arrivals, server=sv)
+    torch.cuda.synchronize()
+    _check(outs, ref)
+    _say(f"replay server={through_server}: p50 {np.percentile(lat, 50):.0f} us, "
+         f"p99 {np.percentile(lat, 99):.0f} us, elapsed {elapsed:.0f} us")
+    assert (lat > 0).all() and elapsed >= arrivals[-1]
+    if sv is not None:
+        assert sv.stats()["requests"] == n
+        sv.close()
+
+
+def test_admission_control(env):
+    pk, torch, codes, plans = env
+    sv = pk.Server(plans, streams=1, max_requests=1, max_pending_frames=5000)
+    big = synth.make_batch(codes[2], 4096, 4.0, (77, 1), "i8")
+    big_llr = torch.from_numpy(big.llr).cuda()
+    small = _requests(torch, codes, 1, 13)[0]
+    t_big, out_big = sv.submit(2, big_llr)
+    with pytest.raises(pk.PsclError) as e:
+        sv.submit(*small)  # the server holds its one request
+    assert e.value.status == 6
+    sv.wait(t_big)
+    t_small, out_small = sv.submit(*small)
+    sv.wait(t_small)
+    with pytest.raises(pk.PsclError) as e:  # larger than the queue admits, ever
+        sv.submit(2, torch.zeros((5001, 1024), dtype=torch.int8, device="cuda"))
+    assert e.value.status == 1
+    torch.cuda.synchronize()
+    _check([out_big, out_small], _alone(torch, plans, [(2, big_llr), small]))
+    sv.close()
