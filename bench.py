@@ -102,6 +102,93 @@ def wilson(k, n, z=1.959964):
     return (max(0.0, c - h), min(1.0, c + h))
 
 
+def c4_codes(synth):
+    """The mixed code set: N in {256..4096}, rate in {1/3, 1/2, 0.84} with
+    K = round(R N) and the CRC inside K (CRC-8 below K = 256, else CRC-32),
+    Bhattacharyya design 2.5 dB for R <= 1/2 and 4.0 dB for R = 0.84 (also
+    the operating Eb/N0: the decoder's work does not depend on it), L in
+    {2, 8, 32}: 45 codes."""
+    out = []
+    for N in (256, 512, 1024, 2048, 4096):
+        for R in (1 / 3, 1 / 2, 0.84):
+            K = round(R * N)
+            r = 8 if K < 256 else 32
+            poly = synth.CRC8_POLY if r == 8 else synth.CRC32_POLY
+            d = 2.5 if R <= 0.5 else 4.0
+            code = synth.make_code(N, K, r, poly, d)
+            for L in (2, 8, 32):
+                out.append((code, L, d))
+    return out
+
+
+def mixed_leg(pk, torch, synth, frames_per_code=1456, reps=3):
+    """One mixed launch over all 45 codes vs one launch per code, int8."""
+    codes = c4_codes(synth)
+    plans, work, bits = [], [], 0
+    for i, (code, L, d) in enumerate(codes):
+        plans.append(pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8"))
+        b = synth.make_batch(code, frames_per_code, d, (4, i), "i8")
+        work.append((i, torch.from_numpy(b.llr).cuda()))
+        bits += frames_per_code * (code.K - code.r)
+    group = pk.Group(plans, max_jobs=len(work), max_inflight=1)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_mixed = timed(lambda: group.decode(work))
+    ms_per_code = timed(lambda: [plans[i].decode(llr) for i, llr in work])
+    group.close()
+    return {"codes": len(codes), "frames": frames_per_code * len(codes), "dtype": "i8",
+            "mixed_launch": {"ms": round(ms_mixed, 3), "gbps": round(bits / ms_mixed / 1e6, 4)},
+            "per_code_launches": {"ms": round(ms_per_code, 3),
+                                  "gbps": round(bits / ms_per_code / 1e6, 4)},
+            "workload": "N in {256..4096} x R in {1/3,1/2,0.84} x L in {2,8,32}, CRC inside K, "
+                        "BPSK-AWGN at each code's design Eb/N0"}
+
+
+def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), span_s=0.25,
+                max_requests=16000, streams=4):
+    """Poisson arrivals of requests of 1..64 frames of a random code of the
+    mixed set (int8), replayed through a server and as plain per-request
+    launches; p50 / p99 latency and sustained payload Gbps."""
+    codes = c4_codes(synth)
+    plans, pool = [], []
+    for i, (code, L, d) in enumerate(codes):
+        plans.append(pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8"))
+        b = synth.make_batch(code, 64, d, (5, i), "i8")
+        pool.append(torch.from_numpy(b.llr).cuda())
+    payload = [c.K - c.r for c, _, _ in codes]
+    rng = np.random.default_rng(2015)
+    out = {}
+    for lam in rates:
+        n = int(min(max_requests, lam * span_s))
+        idx = rng.integers(len(codes), size=n)
+        F = rng.integers(1, 65, size=n)
+        arrivals = np.cumsum(rng.exponential(1e6 / lam, n))
+        work = [(int(i), pool[int(i)][: int(f)]) for i, f in zip(idx, F)]
+        bits = float(sum(payload[int(i)] * int(f) for i, f in zip(idx, F)))
+        row = {"requests": n}
+        for name, sv in (("server", pk.Server(plans, streams=streams)), ("per_request", None)):
+            _, lat, el = pk.replay(plans, work, arrivals, server=sv)
+            torch.cuda.synchronize()
+            row[name] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                         "p99_us": round(float(np.percentile(lat, 99)), 1),
+                         "gbps": round(bits / el / 1e3, 4)}
+            if sv is not None:
+                row[name]["launches"] = sv.stats()["launches"]
+                sv.close()
+        out[f"{int(lam)}"] = row
+    return out
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -120,7 +207,10 @@ def main():
     ap.add_argument("--ebn0", type=float, default=4.0)
     ap.add_argument("--cpu-sample", type=int, default=65536,
                     help="frames the oracle decodes for the CPU baseline (0 = skip)")
-    ap.add_argument("--single", action="store_true", help="time only --dtype")
+    ap.add_argument("--single", action="store_true",
+                    help="time only --dtype (no int8, mixed or serving legs)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -233,9 +323,18 @@ def main():
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
 
+    mixed = serving = None
+    if not args.single and not args.no_mixed:
+        print("[bench] mixed launch vs per-code launches", file=sys.stderr, flush=True)
+        mixed = mixed_leg(pk, torch, synth)
+    if not args.single and not args.no_serving:
+        print("[bench] serving replay", file=sys.stderr, flush=True)
+        serving = serving_leg(pk, torch, synth, np)
+
     info = plan.info()
     out = {
         "metric": "info Gbps @ (2048,1723) CRC32 L=32",
+        "p99_latency_us": None if serving is None else serving["100000"]["server"]["p99_us"],
         "fer_vs_oracle": None if cpu is None else cpu["fer_vs_oracle"],
         "value": round(value, 4),
         "unit": "Gbps",
@@ -255,6 +354,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "other_dtypes": extra,
+        "mixed": mixed,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
