@@ -407,11 +407,13 @@ DEV Grp make_grp(int tid, int NT, int P) {
 }
 
 // Orders this lane's earlier memory operations before its later ones as seen
-// by the other lanes of its wavefront.
+// by the other lanes of its wavefront.  A wavefront's memory operations are
+// performed in order, so at wavefront scope this costs no wait: the fences
+// only keep the compiler from moving memory operations across it.
 DEV void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------
@@ -909,6 +911,18 @@ DEV void pp_rate0_any(const Ctx<T>& c, const OpRec& op, int k, int side, const G
 // order by a bitonic network, E keys per lane (element i = lane * E + t,
 // missing elements padded with key 0, which every real key beats); the first
 // L positions are the survivors, best first.
+// Lanes l of a wavefront with (l & b) == 0, as a mask (b a power of two;
+// b >= 64: every lane).
+DEV constexpr uint64_t lanes_bit_clear(int b) {
+    return b >= 64   ? ~0ull
+           : b == 32 ? 0x00000000ffffffffull
+           : b == 16 ? 0x0000ffff0000ffffull
+           : b == 8  ? 0x00ff00ff00ff00ffull
+           : b == 4  ? 0x0f0f0f0f0f0f0f0full
+           : b == 2  ? 0x3333333333333333ull
+                     : 0x5555555555555555ull;
+}
+
 template <int E>
 DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int L) {
     uint64_t v[E];
@@ -917,6 +931,11 @@ DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int
         const int e = lane * E + t;
         v[t] = e < C ? ck[e] : 0ull;
     }
+    // In a step (k, j) element i keeps the larger of its pair when
+    // (i & k) == 0 and (i & j) == 0 agree.  Once k >= E that is the same
+    // for the E elements of a lane, so each step's direction is a constant
+    // lane mask and a compare-exchange is one 64-bit compare, a mask XOR
+    // and two selects.
     constexpr int CP = 64 * E;
 #pragma unroll
     for (int k = 2; k <= CP; k <<= 1) {
@@ -928,23 +947,30 @@ DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int
                 for (int t = 0; t < E; ++t) {
                     const int l = t ^ j;
                     if (l > t) {
-                        const int i = lane * E + t;
-                        const bool desc = (i & k) == 0;
-                        const uint64_t hi = umax64(v[t], v[l]), lo = umin64(v[t], v[l]);
-                        v[t] = desc ? hi : lo;
-                        v[l] = desc ? lo : hi;
+                        const uint64_t a = v[t], b2 = v[l];
+                        bool keep;  // v[t] keeps the larger key
+                        if (k < E) {
+                            const bool desc = (t & k) == 0;
+                            keep = (a > b2) == desc;
+                        } else {
+                            const uint64_t desc = lanes_bit_clear(k / E);
+                            keep = __builtin_amdgcn_inverse_ballot_w64(~(__ballot(a > b2) ^ desc));
+                        }
+                        v[t] = keep ? a : b2;
+                        v[l] = keep ? b2 : a;
                     }
                 }
             } else {
                 // partner in lane ^ (j / E), same position
                 const int m = j / E;
+                const uint64_t want_max = ~(lanes_bit_clear(k / E) ^ lanes_bit_clear(m));
 #pragma unroll
                 for (int t = 0; t < E; ++t) {
                     uint64_t pa, pb;
                     xpair64_dyn(v[t], m, pa, pb);
-                    const int i = lane * E + t;
-                    const bool want_max = ((i & k) == 0) == ((i & j) == 0);
-                    v[t] = want_max ? umax64(pa, pb) : umin64(pa, pb);
+                    const bool take_a =
+                        __builtin_amdgcn_inverse_ballot_w64(~(__ballot(pa > pb) ^ want_max));
+                    v[t] = take_a ? pa : pb;
                 }
             }
         }
@@ -993,9 +1019,7 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
         if (keep) kept[pos] = key;
         n += (int)__builtin_popcountll(bal);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_sync();
     if (n <= 64) bitonic_select<1>(kept, c.surv(), lane, n, L);
     else if (n <= 128) bitonic_select<2>(kept, c.surv(), lane, n, L);
     else bitonic_select<4>(kept, c.surv(), lane, n, L);
