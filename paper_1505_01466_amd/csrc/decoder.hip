@@ -74,6 +74,11 @@ struct Dom<float> {
         const uint32_t b = __float_as_uint(__fadd_rn(pm, 0.0f));  // -0 -> +0
         return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
     }
+    // inverse of order (metrics are never -0: they start at +0 and only
+    // lose non-negative penalties)
+    static DEV M from_order(uint32_t o) {
+        return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+    }
     static DEV uint32_t bits(M pm) { return __float_as_uint(pm); }
 };
 
@@ -98,6 +103,7 @@ struct DomI {
     static DEV M round_pen(S s) { return s; }
     static DEV M sub(M pm, M pen) { return pm - pen; }
     static DEV uint32_t order(M pm) { return (uint32_t)pm ^ 0x80000000u; }
+    static DEV M from_order(uint32_t o) { return (int)(o ^ 0x80000000u); }
     static DEV uint32_t bits(M pm) { return (uint32_t)pm; }
 };
 template <>
@@ -923,20 +929,17 @@ DEV constexpr uint64_t lanes_bit_clear(int b) {
                      : 0x5555555555555555ull;
 }
 
-template <int E>
-DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int L) {
-    uint64_t v[E];
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-        const int e = lane * E + t;
-        v[t] = e < C ? ck[e] : 0ull;
-    }
+// Sorts the keys v (element i = lane * E + t of NL * E, over lanes
+// 0 .. NL - 1; NL = 32 or 64, lanes beyond NL sort their own values)
+// into descending order.
+template <int E, int NL>
+DEV void bitonic_sort(uint64_t (&v)[E]) {
     // In a step (k, j) element i keeps the larger of its pair when
     // (i & k) == 0 and (i & j) == 0 agree.  Once k >= E that is the same
     // for the E elements of a lane, so each step's direction is a constant
     // lane mask and a compare-exchange is one 64-bit compare, a mask XOR
     // and two selects.
-    constexpr int CP = 64 * E;
+    constexpr int CP = NL * E;
 #pragma unroll
     for (int k = 2; k <= CP; k <<= 1) {
 #pragma unroll
@@ -975,6 +978,17 @@ DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int
             }
         }
     }
+}
+
+template <int E>
+DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int L) {
+    uint64_t v[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int e = lane * E + t;
+        v[t] = e < C ? ck[e] : 0ull;
+    }
+    bitonic_sort<E, 64>(v);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int pos = lane * E + t;
@@ -1087,6 +1101,261 @@ DEV void pp_emit_pending(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
     else if (type == OP_R1) pp_emit_typed<T, OP_R1>(c, op, prune, q);
     else pp_emit_typed<T, OP_SPC>(c, op, prune, q);
     c.cur ^= 1;  // path tables now in the other buffer
+}
+
+// ---------------------------------------------------------------------------
+// Forking leaves of at most 32 values (one partial-sum word), fused in one
+// wavefront.  Lane s scores source path s in registers; the candidates are
+// ranked in registers (repetition: each lane's two keys are already in the
+// order a two-per-lane network expects) or, for Rate-1 / SPC, first
+// compacted below the rank-0 threshold through the key scratch; then the
+// lane holding survivor j writes slot j itself: its metric (recovered from
+// the key), its path tables (its source's rows) and its codeword word.  The
+// candidates, keys and survivors are those of the three-pass form, with one
+// workgroup barrier instead of three and no survivor list.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc, int P) {
+    using D = Dom<T>;
+    using A = typename D::A;
+    using S = typename D::S;
+    using M = typename D::M;
+    const int L = c.L;
+    const int C = P * cc;
+    const int lc = ilog2u(cc);
+    const bool prune = C > L;
+    const int isp = op_isp(op), osp = op_osp(op);
+    // wavefront 0 reads every path's input, which other wavefronts may have
+    // just written
+    if (c.NT > 64) __syncthreads();
+    if (c.tid < 64) {
+        const int lane = c.lane;
+        const bool act = lane < P;
+        const int s = act ? lane : 0;  // idle lanes score path 0 and are ignored
+        const int nv = 1 << k;
+        // the input and output spaces vary by level; generic pointers keep
+        // one copy of this code
+        const T* in = isp == SP_CH    ? c.chan
+                      : isp == SP_LDS ? (const T*)c.template stage<SP_LDS>(op.x, k, c.srcA(k, s))
+                                      : (const T*)c.template stage<SP_WS>(op.x, k, c.srcA(k, s));
+        const bool clamp = isp == SP_CH;
+        const M pms = c.pm()[s];
+        uint64_t key[8];
+        auto put = [&](int r, M v) {
+            key[r] = ((uint64_t)D::order(v) << 32) | (uint32_t)(0xffff - ((s << lc) + r));
+        };
+#pragma unroll
+        for (int r = 0; r < 8; ++r) key[r] = 0ull;
+        uint16_t inf[4] = {0, 0, 0, 0};
+        uint32_t bit4 = 0, hd = 0;
+        // the node's values, one at a time (at most 32)
+        auto scan = [&](auto fn) {
+            using IO = VecIO<T>;
+            if (nv >= IO::V) {
+                for (int ch = 0; ch < (nv >> IO::LOGV); ++ch) {
+                    const uint4 q0 = *(const uint4*)(in + (ch << IO::LOGV));
+                    A v[IO::V];
+                    IO::unpack(q0, v);
+#pragma unroll
+                    for (int j = 0; j < IO::V; ++j)
+                        fn((ch << IO::LOGV) + j, clamp ? D::load(v[j]) : v[j]);
+                }
+            } else {
+                for (int i = 0; i < nv; ++i) fn(i, D::load(in[i]));
+            }
+        };
+        if (type == OP_REP) {
+            // penalties of the all-zero and all-one words (Sec. III-E)
+            S z = 0, o = 0;
+            scan([&](int, A v) {
+                if (v < 0) z += D::widen_abs(v);
+                else o += D::widen_abs(v);
+            });
+            const M zr = D::round_pen(z), orr = D::round_pen(o);
+            const bool one = orr < zr;  // ML word first; equal -> all-zero
+            put(0, D::sub(pms, one ? orr : zr));
+            put(1, D::sub(pms, one ? zr : orr));
+            bit4 = one ? 1u : 0u;
+        } else if (type == OP_R1 && k == 0) {
+            const A v = D::load(in[0]);
+            put(0, pms);
+            put(1, D::sub(pms, D::round_pen(D::widen_abs(v))));
+            bit4 = (v < 0) ? 1u : 0u;
+        } else if (type == OP_R1) {
+            // two least reliable positions, ties to the lower index
+            uint64_t k1 = ~0ull, k2 = ~0ull;
+            scan([&](int i, A v) {
+                hd |= (v < 0 ? 1u : 0u) << i;
+                const uint64_t kv = ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i;
+                const uint64_t lo = umin64(k1, kv);
+                k2 = umin64(umax64(k1, kv), k2);
+                k1 = lo;
+            });
+            const S a1 = D::mag_from_key((uint32_t)(k1 >> 32));
+            const S a2 = D::mag_from_key((uint32_t)(k2 >> 32));
+            put(0, pms);
+            put(1, D::sub(pms, D::round_pen(a1)));
+            put(2, D::sub(pms, D::round_pen(a2)));
+            put(3, D::sub(pms, D::round_pen(a1 + a2)));
+            inf[0] = (uint16_t)(k1 & 0xffff);
+            inf[1] = (uint16_t)(k2 & 0xffff);
+        } else {  // OP_SPC
+            uint64_t kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+            int par = 0;
+            scan([&](int i, A v) {
+                const int b = (v < 0) ? 1 : 0;
+                hd |= (uint32_t)b << i;
+                par ^= b;
+                insert4(kk, ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i);
+            });
+            // the four positions re-sorted by index (carrying their
+            // reliability rank), so penalties sum in index order
+            uint32_t idx[4], rk[4];
+            S mag[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                idx[t] = (uint32_t)(kk[t] & 0xffff);
+                mag[t] = D::mag_from_key((uint32_t)(kk[t] >> 32));
+                rk[t] = (uint32_t)t;
+                inf[t] = (uint16_t)idx[t];
+            }
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+#pragma unroll
+                for (int y = 0; y < 3 - x; ++y) {
+                    const bool sw = idx[y] > idx[y + 1];
+                    const uint32_t i0 = idx[y], i1 = idx[y + 1];
+                    const uint32_t r0 = rk[y], r1 = rk[y + 1];
+                    const S m0 = mag[y], m1 = mag[y + 1];
+                    idx[y] = sw ? i1 : i0;
+                    idx[y + 1] = sw ? i0 : i1;
+                    rk[y] = sw ? r1 : r0;
+                    rk[y + 1] = sw ? r0 : r1;
+                    mag[y] = sw ? m1 : m0;
+                    mag[y + 1] = sw ? m0 : m1;
+                }
+            }
+            bit4 = (uint32_t)par;
+            const uint32_t base_d = par ? 1u : 0u;  // ML flips m1 when parity fails
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (r < cc) {
+                    const uint32_t dm = spc_flips(r) ^ base_d;
+                    S pen = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if ((dm >> rk[t]) & 1u) pen += mag[t];
+                    put(r, D::sub(pms, D::round_pen(pen)));
+                }
+            }
+        }
+        // what a survivor's writer needs from its source
+        if (act) {
+            uint16_t* si = c.sinfo() + s * 8;
+            si[0] = inf[0];
+            si[1] = inf[1];
+            si[2] = inf[2];
+            si[3] = inf[3];
+            si[4] = (uint16_t)bit4;
+            si[6] = (uint16_t)hd;
+            si[7] = (uint16_t)(hd >> 16);
+        }
+        const uint32_t full = nv >= 32 ? 0xffffffffu : ((1u << nv) - 1u);
+        const int nxt = c.cur ^ 1;
+        const bool whole = type == OP_REP || (type == OP_R1 && k == 0);
+        const int nflip = type == OP_R1 ? 2 : 4;
+        // writes slot j from the candidate with key kv
+        auto emit = [&](int j, uint64_t kv) {
+            const int e = 0xffff - (int)(kv & 0xffff);
+            const int src = e >> lc;
+            const int r = e & (cc - 1);
+            const uint16_t* sj = c.sinfo() + src * 8;
+            uint32_t word;
+            if (whole) {
+                word = ((sj[4] ^ r) & 1) ? full : 0u;
+            } else {
+                word = (uint32_t)sj[6] | ((uint32_t)sj[7] << 16);
+                const uint32_t dm = type == OP_R1 ? (uint32_t)r : (spc_flips(r) ^ (sj[4] ? 1u : 0u));
+                for (int t = 0; t < nflip; ++t)
+                    if ((dm >> t) & 1u) word ^= 1u << sj[t];
+            }
+            uint32_t* o = osp == SP_LDS ? c.template bw<SP_LDS>(op.y, k, j)
+                                        : c.template bw<SP_WS>(op.y, k, j);
+            *o = word;
+            *(uint4*)c.rowA(nxt, j) = *(const uint4*)c.rowA(c.cur, src);
+            *(uint4*)c.rowB(nxt, j) = *(const uint4*)c.rowB(c.cur, src);
+            if (side == 0) c.rowB(nxt, j)[k] = (uint8_t)j;
+            c.pm()[j] = D::from_order((uint32_t)(kv >> 32));
+        };
+        wave_sync();
+        if (!prune) {
+            // every candidate survives, in enumeration order
+            if (act)
+                for (int r = 0; r < cc; ++r) {
+                    uint64_t kv = key[0];
+#pragma unroll
+                    for (int t = 1; t < 8; ++t) kv = r == t ? key[t] : kv;
+                    emit((s << lc) + r, kv);
+                }
+        } else if (type == OP_REP) {
+            // two keys per lane, source s's at positions 2s, 2s + 1
+            uint64_t v[2] = {act ? key[0] : 0ull, act ? key[1] : 0ull};
+            bitonic_sort<2, 32>(v);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int pos = lane * 2 + t;
+                if (lane < 32 && pos < L) emit(pos, v[t]);
+            }
+        } else {
+            // keys through the scratch, dropped below the rank-0 threshold
+            // when every slot holds a path, compacted, sorted
+            uint64_t* ck = c.ckey();
+            if (act) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (r < cc) ck[(s << lc) + r] = key[r];
+            }
+            uint64_t t0 = 0ull;
+            if (P == L) {
+                uint64_t v = act ? key[0] : ~0ull;
+                xor_steps(64, [&](auto mc) {
+                    uint64_t pa, pb;
+                    xpair64<decltype(mc)::value>(v, pa, pb);
+                    v = umin64(pa, pb);
+                });
+                t0 = v;
+            }
+            wave_sync();
+            int n = 0;
+            for (int base = 0; base < C; base += 64) {
+                const int e = base + lane;
+                const uint64_t kv = e < C ? ck[e] : 0ull;
+                const bool keep = e < C && kv >= t0;
+                const uint64_t bal = __ballot(keep);
+                const int pos = n + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
+                if (keep) ck[pos] = kv;
+                n += (int)__builtin_popcountll(bal);
+            }
+            wave_sync();
+            if (n <= 64) {
+                uint64_t v[1] = {lane < n ? ck[lane] : 0ull};
+                bitonic_sort<1, 64>(v);
+                if (lane < L) emit(lane, v[0]);
+            } else {
+                // at most 8 L = 256 keys, four per lane
+                uint64_t v[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[t] = lane * 4 + t < n ? ck[lane * 4 + t] : 0ull;
+                bitonic_sort<4, 64>(v);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (lane * 4 + t < L) emit(lane * 4 + t, v[t]);
+            }
+        }
+    }
+    c.cur ^= 1;  // path tables now in the other buffer (every thread)
+    return prune ? L : C;
 }
 
 // ---------------------------------------------------------------------------
@@ -1298,6 +1567,17 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                 pp_rate0_any<T>(c, op, k, side, q);
                 break;
             default: {
+                if constexpr (std::is_same<T, float>::value) {
+                    // a short forking leaf: fused in one wavefront (measured
+                    // faster for float32 only, whose workgroups span two
+                    // wavefronts)
+                    if (k <= 5) {
+                        P = fork_small<T>(c, op, type, k, side, cc, P);
+                        q = make_grp(c.tid, c.NT, P);
+                        __syncthreads();
+                        break;
+                    }
+                }
                 // a forking leaf: score, select across the workgroup, and
                 // leave the survivors to be written by their new owners
                 if (type == OP_REP) pp_fork_score_any<T, OP_REP>(c, op, k, cc, q);
