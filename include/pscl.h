@@ -119,12 +119,13 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
 
 /*
  * Launch shape of a plan.  A zero field takes the library default for the
- * dtype (float32: 128 threads, 20 KiB; int16: 64 threads, 10 KiB; int8: 64
- * threads, 12 KiB, chosen by measurement at (2048,1723) L=32), which the
- * environment variables PSCL_THREADS and PSCL_LDS_BUDGET override.
+ * dtype (float32: 128 threads, 24 KiB; int16: 64 threads, 12 KiB; int8: 64
+ * threads, 10 KiB, chosen by measurement at (2048,1723) L=32), which the
+ * environment variables PSCL_THREADS, PSCL_LDS_BUDGET and
+ * PSCL_MAX_WG_PER_CU override.
  *   threads: threads per workgroup (one frame per workgroup): 64, 128, 256,
  *            512 or 1024.
- *   lds_budget: LDS bytes per workgroup for the path tables, candidate
+ *   lds_budget: LDS bytes per workgroup (one frame) for the path tables, candidate
  *            scratch and the low tree levels' LLR stages and partial sums;
  *            the levels that do not fit go to the global workspace.  A
  *            budget too small for the tables alone is raised to the
@@ -133,6 +134,7 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
 typedef struct {
     int threads;
     int lds_budget;
+    int max_wg_per_cu; /* resident workgroups per CU at most (0 = as many as fit) */
 } pscl_launch_cfg;
 
 /* pscl_plan_create with an explicit launch shape (cfg may be NULL).
@@ -309,6 +311,33 @@ pscl_status pscl_server_stats(pscl_server* server, int64_t* requests, int64_t* f
 pscl_status pscl_replay(pscl_server* server, const pscl_plan* const* plans, int n_plans,
                         const pscl_job* jobs, const double* arrival_us, int n, void* stream,
                         double* latency_us, double* elapsed_us);
+
+/*
+ * Adaptive decoding (Sec. VI): every frame is decoded first by `fast`, a
+ * plan with L = 1 (Fast-SSC on the same tree), and only the frames whose
+ * CRC fails are decoded again by `list`.  Both plans must be of the same
+ * code (N, frozen set, K, CRC, which must be present) and dtype, and must
+ * outlive the adaptive decoder; `fast` must have L = 1 (PSCL_E_INVALID
+ * otherwise).  max_frames bounds F per call.  Allocates the index scratch.
+ */
+typedef struct pscl_adaptive pscl_adaptive;
+pscl_status pscl_adaptive_create(const pscl_plan* fast, const pscl_plan* list, int64_t max_frames,
+                                 pscl_adaptive** out);
+
+/* Release (NULL allowed); synchronises the device first. */
+void pscl_adaptive_destroy(pscl_adaptive* ad);
+
+/*
+ * Decode F frames (F <= max_frames) with the buffers and rules of
+ * pscl_decode: a frame's outputs are the fast pass's if its CRC passes,
+ * else the list pass's (crc_ok, pm then describe the list pass).  Nothing
+ * returns to the host in between: the failing frames are gathered on the
+ * device.  n_list (device int64, NULL allowed) receives the number of
+ * frames list-decoded.  Calls on one adaptive decoder must be ordered
+ * (they share its scratch and the plans' workspaces).
+ */
+pscl_status pscl_adaptive_decode(pscl_adaptive* ad, const void* llr, int64_t F, uint8_t* u_hat,
+                                 uint8_t* crc_ok, void* pm, int64_t* n_list, void* stream);
 
 /* Launch shape chosen for a plan: frames per workgroup, threads per
  * workgroup, workgroups, LDS bytes per workgroup, bytes of global workspace,

@@ -7,6 +7,7 @@ The decoder is the C-ABI library ``_lib/libpscl.so`` (declared in
 
 from ._binding import (  # noqa: F401
     DTYPES,
+    Adaptive,
     LIB_PATH,
     Group,
     Job,

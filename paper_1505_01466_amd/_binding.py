@@ -41,7 +41,8 @@ class PsclError(RuntimeError):
 class LaunchCfg(ctypes.Structure):
     """pscl_launch_cfg: threads per workgroup and LDS budget (0 = default)."""
 
-    _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int)]
+    _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int),
+                ("max_wg_per_cu", ctypes.c_int)]
 
 
 class Job(ctypes.Structure):
@@ -122,6 +123,12 @@ def _load():
     lib.pscl_replay.argtypes = [vp, ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), dp, c_int, vp,
                                 dp, dp]
     lib.pscl_replay.restype = c_int
+    lib.pscl_adaptive_create.argtypes = [vp, vp, c_i64, ctypes.POINTER(vp)]
+    lib.pscl_adaptive_create.restype = c_int
+    lib.pscl_adaptive_destroy.argtypes = [vp]
+    lib.pscl_adaptive_destroy.restype = None
+    lib.pscl_adaptive_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp, vp]
+    lib.pscl_adaptive_decode.restype = c_int
     return lib
 
 
@@ -165,7 +172,7 @@ class Plan:
 
     def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int,
                  dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE,
-                 threads: int = 0, lds_budget: int = 0):
+                 threads: int = 0, lds_budget: int = 0, max_wg_per_cu: int = 0):
         import torch
 
         if dtype not in DTYPES:
@@ -175,7 +182,7 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device())
         fz = _mask(frozen)
         h = ctypes.c_void_p(None)
-        cfg = LaunchCfg(threads, lds_budget)
+        cfg = LaunchCfg(threads, lds_budget, max_wg_per_cu)
         _check(lib.pscl_plan_create_cfg(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype],
                                         spc_max, mode, ctypes.byref(cfg), ctypes.byref(h)),
                "pscl_plan_create_cfg")
@@ -248,12 +255,13 @@ def autotune(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr,
     if llr.dim() != 2 or llr.shape[1] != N or not llr.is_contiguous():
         raise ValueError(f"llr must be a contiguous F x {N} tensor")
     fz = _mask(frozen)
-    best = LaunchCfg(0, 0)
+    best = LaunchCfg(0, 0, 0)
     ms = ctypes.c_float(0.0)
     _check(lib.pscl_autotune(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype], spc_max, mode,
                              llr.data_ptr(), llr.shape[0], _stream_handle(llr.device),
                              ctypes.byref(best), ctypes.byref(ms)), "pscl_autotune")
-    return {"threads": best.threads, "lds_budget": best.lds_budget}, ms.value
+    return ({"threads": best.threads, "lds_budget": best.lds_budget,
+             "max_wg_per_cu": best.max_wg_per_cu}, ms.value)
 
 
 def _jobs(plans, work):
@@ -285,7 +293,7 @@ class Group:
     def __init__(self, plans, max_jobs: int = 64, max_inflight: int = 4, threads: int = 0):
         self.plans = list(plans)
         hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
-        cfg = LaunchCfg(threads, 0)
+        cfg = LaunchCfg(threads, 0, 0)
         h = ctypes.c_void_p(None)
         _check(lib.pscl_group_create(hs, len(self.plans), max_jobs, max_inflight,
                                      ctypes.byref(cfg), ctypes.byref(h)), "pscl_group_create")
@@ -407,3 +415,51 @@ def replay(plans, work, arrival_us, server=None):
                            _stream_handle(plans[0].device), lat.ctypes.data_as(dp),
                            ctypes.byref(el)), "pscl_replay")
     return outs, lat, el.value
+
+
+class Adaptive:
+    """Adaptive decoding (see pscl_adaptive_create): `fast` (an L = 1 plan)
+    first, `list` for the frames whose CRC fails.  The plans must outlive it."""
+
+    def __init__(self, fast: Plan, list_plan: Plan, max_frames: int):
+        self.fast, self.list = fast, list_plan
+        h = ctypes.c_void_p(None)
+        _check(lib.pscl_adaptive_create(fast._h, list_plan._h, max_frames, ctypes.byref(h)),
+               "pscl_adaptive_create")
+        self._h = h
+
+    def decode(self, llr, u_hat=None, crc_ok=None, pm=None, n_list=None):
+        """-> (u_hat, crc_ok, pm, n_list) with n_list a one-element int64 device
+        tensor: the frames that were list-decoded."""
+        import torch
+
+        p = self.list
+        want = {"f32": torch.float32, "i16": torch.int16, "i8": torch.int8}[p.dtype]
+        if llr.dtype != want or llr.dim() != 2 or llr.shape[1] != p.N or not llr.is_contiguous():
+            raise ValueError(f"llr must be a contiguous F x {p.N} {want} tensor")
+        F = llr.shape[0]
+        dev = llr.device
+        if u_hat is None:
+            u_hat = torch.empty((F, p.K), dtype=torch.uint8, device=dev)
+        if crc_ok is None:
+            crc_ok = torch.empty(F, dtype=torch.uint8, device=dev)
+        if pm is None:
+            pm = torch.empty(F, dtype=torch.float32 if p.dtype == "f32" else torch.int32,
+                             device=dev)
+        if n_list is None:
+            n_list = torch.zeros(1, dtype=torch.int64, device=dev)
+        _check(lib.pscl_adaptive_decode(self._h, llr.data_ptr(), F, u_hat.data_ptr(),
+                                        crc_ok.data_ptr(), pm.data_ptr(), n_list.data_ptr(),
+                                        _stream_handle(dev)), "pscl_adaptive_decode")
+        return u_hat, crc_ok, pm, n_list
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pscl_adaptive_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

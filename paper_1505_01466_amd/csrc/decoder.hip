@@ -332,8 +332,9 @@ struct KArgs {
     int64_t ws_frame;  // workspace bytes per workgroup
     int n_ops, N, n, K, L, has_crc;
     int ptrA_off, ptrB_off, pm_off, root_off, root_sp;
+    int rs;  // bytes per path-table row (one byte per tree level, 4-aligned)
     // candidate scratch
-    int cpm_off, ckey_off, surv_off, sinfo_off;
+    int spm_off, ckey_off, surv_off, sinfo_off;
 };
 
 DEV int words_of(int k) { return k >= 5 ? (1 << (k - 5)) : 1; }
@@ -346,21 +347,27 @@ struct Ctx {
     uint8_t* wsb;
     const T* chan;  // the frame's channel LLRs
     int N, n, L, tid, NT, lane;
-    int ptrA_off, ptrB_off, pm_off;
-    int cpm_off, ckey_off, surv_off, sinfo_off;
+    int ptrA_off, ptrB_off, pm_off, rs;
+    int spm_off, ckey_off, surv_off, sinfo_off;
     int cur;  // which copy of the path tables is current
 
     // Path -> buffer tables, one 16-byte row per slot (entry k = tree level
     // k), double-buffered so that a selection can rebuild them from the old
     // rows.  ptrA maps LLR stages, ptrB left partial sums.
-    DEV uint8_t* rowA(int buf, int slot) const { return lds + ptrA_off + ((buf * L + slot) << 4); }
-    DEV uint8_t* rowB(int buf, int slot) const { return lds + ptrB_off + ((buf * L + slot) << 4); }
+    DEV uint8_t* rowA(int buf, int slot) const { return lds + ptrA_off + (buf * L + slot) * rs; }
+    DEV uint8_t* rowB(int buf, int slot) const { return lds + ptrB_off + (buf * L + slot) * rs; }
+    // copies a row (rs / 4 words)
+    DEV void copy_row(uint8_t* dst, const uint8_t* src) const {
+#pragma unroll 1
+        for (int w = 0; w < (rs >> 2); ++w) ((uint32_t*)dst)[w] = ((const uint32_t*)src)[w];
+    }
     DEV int srcA(int k, int slot) const { return rowA(cur, slot)[k]; }
     DEV int srcB(int k, int slot) const { return rowB(cur, slot)[k]; }
     DEV void setA(int k, int slot) const { rowA(cur, slot)[k] = (uint8_t)slot; }
     DEV void setB(int k, int slot) const { rowB(cur, slot)[k] = (uint8_t)slot; }
     DEV typename Dom<T>::M* pm() const { return (typename Dom<T>::M*)(lds + pm_off); }
-    DEV typename Dom<T>::M* cpm() const { return (typename Dom<T>::M*)(lds + cpm_off); }
+    // the survivors' ranking keys after a pruning selection, by slot
+    DEV uint64_t* skey() const { return (uint64_t*)(lds + spm_off); }
     DEV uint64_t* ckey() const { return (uint64_t*)(lds + ckey_off); }
     DEV uint16_t* surv() const { return (uint16_t*)(lds + surv_off); }
     DEV uint16_t* sinfo() const { return (uint16_t*)(lds + sinfo_off); }
@@ -770,12 +777,10 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
     const int lc = ilog2u(ccount);
     const int s = q.p;
     const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, s));
-    M* cp = c.cpm() + (s << lc);
     uint64_t* ck = c.ckey() + (s << lc);
     uint16_t* si = c.sinfo() + s * 8;
     const M pms = c.pm()[s];
     auto put = [&](int r, M v) {
-        cp[r] = v;
         ck[r] = ((uint64_t)D::order(v) << 32) | (uint32_t)(0xffff - ((s << lc) + r));
     };
     if constexpr (TYPE == OP_REP) {
@@ -981,7 +986,7 @@ DEV void bitonic_sort(uint64_t (&v)[E]) {
 }
 
 template <int E>
-DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int L) {
+DEV void bitonic_select(const uint64_t* ck, uint64_t* skey, int lane, int C, int L) {
     uint64_t v[E];
 #pragma unroll
     for (int t = 0; t < E; ++t) {
@@ -992,7 +997,7 @@ DEV void bitonic_select(const uint64_t* ck, uint16_t* surv, int lane, int C, int
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int pos = lane * E + t;
-        if (pos < L) surv[pos] = (uint16_t)(0xffff - (uint32_t)(v[t] & 0xffff));
+        if (pos < L) skey[pos] = v[t];
     }
 }
 
@@ -1007,7 +1012,7 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
     const int lane = c.lane;
     uint64_t* ck = c.ckey();
     if (C <= 64) {
-        bitonic_select<1>(ck, c.surv(), lane, C, L);
+        bitonic_select<1>(ck, c.skey(), lane, C, L);
         return;
     }
     uint64_t t0 = 0ull;
@@ -1034,9 +1039,9 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
         n += (int)__builtin_popcountll(bal);
     }
     wave_sync();
-    if (n <= 64) bitonic_select<1>(kept, c.surv(), lane, n, L);
-    else if (n <= 128) bitonic_select<2>(kept, c.surv(), lane, n, L);
-    else bitonic_select<4>(kept, c.surv(), lane, n, L);
+    if (n <= 64) bitonic_select<1>(kept, c.skey(), lane, n, L);
+    else if (n <= 128) bitonic_select<2>(kept, c.skey(), lane, n, L);
+    else bitonic_select<4>(kept, c.skey(), lane, n, L);
 }
 
 // Pass 3 of a forking leaf for one destination slot j: its metric, its path
@@ -1049,7 +1054,10 @@ DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, b
     const int nv = 1 << k;
     const int lc = ilog2u(ccount);
     const int j = q.p;
-    const int e = prune ? c.surv()[j] : j;
+    // the candidate taking slot j and its key (nothing dropped: candidate j,
+    // whose key is intact)
+    const uint64_t kj = prune ? c.skey()[j] : c.ckey()[j];
+    const int e = prune ? 0xffff - (int)(kj & 0xffff) : j;
     const int s = e >> lc;
     const int r = e & (ccount - 1);
     const uint16_t* si = c.sinfo() + s * 8;
@@ -1076,10 +1084,12 @@ DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, b
     }
     if (q.g == 0) {
         const int nxt = c.cur ^ 1;
-        *(uint4*)c.rowA(nxt, j) = *(const uint4*)c.rowA(c.cur, s);
-        *(uint4*)c.rowB(nxt, j) = *(const uint4*)c.rowB(c.cur, s);
+        c.copy_row(c.rowA(nxt, j), c.rowA(c.cur, s));
+        c.copy_row(c.rowB(nxt, j), c.rowB(c.cur, s));
         if (side == 0) c.rowB(nxt, j)[k] = (uint8_t)j;
-        c.pm()[j] = c.cpm()[e];
+        // a survivor's metric: from the selection, or (nothing dropped)
+        // from its intact ranking key
+        c.pm()[j] = Dom<T>::from_order((uint32_t)(kj >> 32));
     }
 }
 
@@ -1283,8 +1293,8 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
             uint32_t* o = osp == SP_LDS ? c.template bw<SP_LDS>(op.y, k, j)
                                         : c.template bw<SP_WS>(op.y, k, j);
             *o = word;
-            *(uint4*)c.rowA(nxt, j) = *(const uint4*)c.rowA(c.cur, src);
-            *(uint4*)c.rowB(nxt, j) = *(const uint4*)c.rowB(c.cur, src);
+            c.copy_row(c.rowA(nxt, j), c.rowA(c.cur, src));
+            c.copy_row(c.rowB(nxt, j), c.rowB(c.cur, src));
             if (side == 0) c.rowB(nxt, j)[k] = (uint8_t)j;
             c.pm()[j] = D::from_order((uint32_t)(kv >> 32));
         };
@@ -1511,7 +1521,8 @@ DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
     c.ptrA_off = a.ptrA_off;
     c.ptrB_off = a.ptrB_off;
     c.pm_off = a.pm_off;
-    c.cpm_off = a.cpm_off;
+    c.spm_off = a.spm_off;
+    c.rs = a.rs;
     c.ckey_off = a.ckey_off;
     c.surv_off = a.surv_off;
     c.sinfo_off = a.sinfo_off;
@@ -1610,20 +1621,39 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
 // The kernels: persistent grids; each workgroup decodes one frame at a time.
 // ---------------------------------------------------------------------------
 
-// One code: frames blockIdx.x, blockIdx.x + gridDim.x, ...
+// Hands out work items one at a time from a device counter (vector
+// atomics): a workgroup that becomes resident only after others have
+// finished simply finds fewer items left, so the launch never waits on a
+// fixed share of a late workgroup.
+struct WorkCounter {
+    unsigned long long* counter;
+    DEV int64_t next(int tid, long long& slot) const {
+        if (tid == 0) slot = (long long)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t g = slot;
+        __syncthreads();
+        return g;
+    }
+};
+
+// One code: frames taken from the counter, any workgroup any frame.
 template <typename T>
 __global__ void __launch_bounds__(1024)
     decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
                   uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
-                  void* __restrict__ pm_out) {
+                  void* __restrict__ pm_out, unsigned long long* __restrict__ counter) {
     extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ long long slot;
     Ctx<T> c;
     c.lds = lds;
     c.tid = threadIdx.x;
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
     bind_plan(c, a, a.ws + (int64_t)blockIdx.x * a.ws_frame);
-    for (int64_t f = blockIdx.x; f < F; f += gridDim.x) {
+    const WorkCounter wc{counter};
+    for (;;) {
+        const int64_t f = wc.next(c.tid, slot);
+        if (f >= F) break;
         c.chan = llr + f * a.N;
         decode_frame(c, a, sched, f, u_hat, crc_ok, pm_out);
     }
@@ -1655,18 +1685,16 @@ __global__ void __launch_bounds__(1024)
                         uint8_t* __restrict__ ws, int64_t ws_frame,
                         unsigned long long* __restrict__ counter) {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ long long next_frame;
+    __shared__ long long slot;
     Ctx<T> c;
     c.lds = lds;
     c.tid = threadIdx.x;
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
     uint8_t* wsb = ws + (int64_t)blockIdx.x * ws_frame;
+    const WorkCounter wc{counter};
     for (;;) {
-        if (c.tid == 0) next_frame = (long long)atomicAdd(counter, 1ull);
-        __syncthreads();
-        const int64_t g = next_frame;
-        __syncthreads();
+        const int64_t g = wc.next(c.tid, slot);
         if (g >= total) break;
         int lo = 0, hi = n_jobs - 1;
         while (lo < hi) {
@@ -1685,6 +1713,49 @@ __global__ void __launch_bounds__(1024)
 }
 
 __global__ void zero_counter(unsigned long long* counter) { *counter = 0ull; }
+
+// ---------------------------------------------------------------------------
+// Adaptive decoding (Sec. VI): after a single-path pass over every frame,
+// the frames whose CRC failed are gathered and list-decoded again.
+// ---------------------------------------------------------------------------
+
+// Indices of the frames with crc_ok == 0, in no particular order.
+__global__ void gather_failed(const uint8_t* __restrict__ crc_ok, int64_t F,
+                              int64_t* __restrict__ idx, unsigned long long* __restrict__ count) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < F && crc_ok[f] == 0) idx[atomicAdd(count, 1ull)] = f;
+}
+
+// The gathered frames, each written back at its own index.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    decode_gathered_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr,
+                           const int64_t* __restrict__ idx,
+                           const unsigned long long* __restrict__ count,
+                           uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
+                           void* __restrict__ pm_out, unsigned long long* __restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ long long slot;
+    Ctx<T> c;
+    c.lds = lds;
+    c.tid = threadIdx.x;
+    c.NT = blockDim.x;
+    c.lane = threadIdx.x & 63;
+    bind_plan(c, a, a.ws + (int64_t)blockIdx.x * a.ws_frame);
+    const int64_t n = (int64_t)*count;
+    const WorkCounter wc{counter};
+    for (;;) {
+        const int64_t i = wc.next(c.tid, slot);
+        if (i >= n) break;
+        const int64_t f = idx[i];
+        c.chan = llr + f * a.N;
+        decode_frame(c, a, sched, f, u_hat, crc_ok, pm_out);
+    }
+}
+
+__global__ void copy_count(const unsigned long long* __restrict__ count, int64_t* __restrict__ out) {
+    *out = (int64_t)*count;
+}
 
 // ---------------------------------------------------------------------------
 // Host side.
@@ -1707,10 +1778,22 @@ struct pscl_plan {
     uint64_t* d_syn = nullptr;
     uint16_t* d_info = nullptr;
     uint8_t* d_ws = nullptr;
+    unsigned long long* d_counter = nullptr;  // frames handed out
     KArgs args{};
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int64_t ws_bytes = 0;
     const void* kernel = nullptr;
+    std::vector<uint8_t> frozen;
+};
+
+struct pscl_adaptive {
+    const pscl_plan* fast = nullptr;
+    const pscl_plan* list = nullptr;
+    int64_t max_frames = 0;
+    int64_t* d_idx = nullptr;
+    unsigned long long* d_count = nullptr;  // frames gathered
+    unsigned long long* d_next = nullptr;   // gathered frames handed out
+    uint8_t* d_ok = nullptr;  // CRC flags when the caller wants none
 };
 
 struct pscl_group {
@@ -1785,20 +1868,22 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
         if (k < n) lay.bl_off[k] = place(bytes, k < k_glob);  // the root is never a left child
         lay.br_off[k] = place(bytes, k < k_glob);
     }
+    // path tables: one byte per tree level 0..n, rows padded to words
+    a.rs = (n + 1 + 3) & ~3;
     a.ptrA_off = off;
-    off = align16(off + 2 * 16 * L);
+    off = align16(off + 2 * a.rs * L);
     a.ptrB_off = off;
-    off = align16(off + 2 * 16 * L);
+    off = align16(off + 2 * a.rs * L);
     a.pm_off = off;
     off = align16(off + 4 * L);
-    // candidate scratch: metrics and ranking keys of up to 8 candidates per
-    // path, survivors, per-source statistics
-    a.cpm_off = off;
-    off = align16(off + 4 * 8 * L);
+    // candidate scratch: ranking keys of up to 8 candidates per path, the
+    // survivors and their metrics, per-source statistics
     a.ckey_off = off;
     off = align16(off + 8 * 8 * L);
-    a.surv_off = off;
-    off = align16(off + 2 * 8 * L);
+    a.surv_off = off;  // pass flags of the final pick
+    off = align16(off + 2 * L);
+    a.spm_off = off;  // survivors' keys
+    off = align16(off + 8 * L);
     a.sinfo_off = off;
     off = align16(off + 16 * L);
     a.root_off = lay.br_off[n];
@@ -1843,12 +1928,12 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
 
 }  // namespace
 
-// Default launch shape per dtype (measured at (2048,1723) L=32): few waves
-// per frame, since every schedule operation costs each wave its control
-// overhead and more resident frames per CU hide each frame's dependent
-// chain better than more waves per frame; an LDS budget that keeps the
-// levels up to 2^5..2^6 on chip without lowering the number of resident
-// workgroups.  PSCL_THREADS / PSCL_LDS_BUDGET override.
+// Default launch shape per dtype (measured at (2048,1723) L=32, 65536
+// frames): few waves per frame, since every schedule operation costs each
+// wave its control overhead and more resident frames per CU hide each
+// frame's dependent chain better than more waves per frame; an LDS budget
+// that keeps tree levels up to 2^5 (int8, int16) or 2^6 (float32) on chip.
+// PSCL_THREADS / PSCL_LDS_BUDGET / PSCL_MAX_WG_PER_CU override.
 // Groups made by pscl_decode_mixed for a set of plans, kept until one of
 // those plans is destroyed.
 static std::mutex g_group_mu;
@@ -1870,11 +1955,13 @@ static void drop_cached_groups(const pscl_plan* p) {
     for (pscl_group* g : dead) pscl_group_destroy(g);
 }
 
-static void default_launch(int dtype, int& threads, int& budget) {
+static void default_launch(int dtype, int& threads, int& budget, int& wg_cap) {
     threads = dtype == PSCL_F32 ? 128 : 64;
-    budget = dtype == PSCL_F32 ? 20 * 1024 : (dtype == PSCL_I16 ? 10 * 1024 : 12 * 1024);
+    budget = dtype == PSCL_F32 ? 24 * 1024 : (dtype == PSCL_I16 ? 12 * 1024 : 10 * 1024);
+    wg_cap = 0;
     if (const char* e = getenv("PSCL_THREADS")) threads = atoi(e);
     if (const char* e = getenv("PSCL_LDS_BUDGET")) budget = atoi(e);
+    if (const char* e = getenv("PSCL_MAX_WG_PER_CU")) wg_cap = atoi(e);
 }
 
 extern "C" {
@@ -1927,6 +2014,7 @@ void pscl_plan_destroy(pscl_plan* p) {
     (void)hipFree(p->d_syn);
     (void)hipFree(p->d_info);
     (void)hipFree(p->d_ws);
+    (void)hipFree(p->d_counter);
     if (cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
@@ -1945,12 +2033,13 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (N < 2 || N > 4096 || (N & (N - 1))) return PSCL_E_INVALID;
     if (!valid_L(L) || dtype < PSCL_F32 || dtype > PSCL_I8) return PSCL_E_INVALID;
     if (mode != PSCL_MODE_TREE && mode != PSCL_MODE_SCL_LEAVES) return PSCL_E_INVALID;
-    int NT = 0, budget = 0;
-    default_launch(dtype, NT, budget);
+    int NT = 0, budget = 0, wg_cap = 0;
+    default_launch(dtype, NT, budget, wg_cap);
     if (cfg && cfg->threads) NT = cfg->threads;
     if (cfg && cfg->lds_budget) budget = cfg->lds_budget;
+    if (cfg && cfg->max_wg_per_cu) wg_cap = cfg->max_wg_per_cu;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
-    if (budget < 0) return PSCL_E_INVALID;
+    if (budget < 0 || wg_cap < 0) return PSCL_E_INVALID;
     int kk = 0;
     for (int i = 0; i < N; ++i) kk += frozen_mask[i] ? 0 : 1;
     if (kk != K || K < 1 || crc_len < 0 || crc_len > 64 || crc_len > K) return PSCL_E_INVALID;
@@ -1971,6 +2060,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     p->mode = mode;
     p->poly = crc_poly;
     p->device = dev;
+    p->frozen.assign(frozen_mask, frozen_mask + N);
     while ((1 << p->n) < N) p->n++;
     if (!build_schedule(N, frozen_mask, L, spc_max, mode, p->sched)) {
         delete p;
@@ -2021,6 +2111,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     int occ = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, p->kernel, p->NT, p->lds_bytes);
     if (e != hipSuccess || occ < 1) occ = 1;
+    if (wg_cap > 0 && occ > wg_cap) occ = wg_cap;
     p->grid_max = occ * prop.multiProcessorCount;
     p->ws_bytes = wsf * (int64_t)p->grid_max;
 
@@ -2042,6 +2133,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     up((void**)&p->d_syn, syn.data(), syn.size() * 8);
     up((void**)&p->d_info, info.data(), info.size() * 2);
     if (st == PSCL_OK && p->ws_bytes > 0) st = hip_status(hipMalloc((void**)&p->d_ws, p->ws_bytes));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&p->d_counter, 8));
     if (st != PSCL_OK) {
         pscl_plan_destroy(p);
         return st;
@@ -2086,21 +2178,24 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     if (e != hipSuccess) return PSCL_E_HIP;
     const int grid = (int)std::min<int64_t>(F, p->grid_max);
     hipStream_t s = (hipStream_t)stream;
+    // the frame counter starts at zero (a one-thread kernel, so that the
+    // call can be captured in a graph)
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, p->d_counter);
     switch (p->dtype) {
         case PSCL_F32:
             hipLaunchKernelGGL(decode_kernel<float>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
                                p->args, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat,
-                               crc_ok, pm);
+                               crc_ok, pm, p->d_counter);
             break;
         case PSCL_I16:
             hipLaunchKernelGGL(decode_kernel<int16_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
                                p->args, (const uint64_t*)p->d_ops, (const int16_t*)llr, F, u_hat,
-                               crc_ok, pm);
+                               crc_ok, pm, p->d_counter);
             break;
         default:
             hipLaunchKernelGGL(decode_kernel<int8_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
                                p->args, (const uint64_t*)p->d_ops, (const int8_t*)llr, F, u_hat,
-                               crc_ok, pm);
+                               crc_ok, pm, p->d_counter);
             break;
     }
     e = hipGetLastError();
@@ -2157,7 +2252,7 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     for (int t : threads) {
         for (int b : budgets) {
             if (st != PSCL_OK) break;
-            pscl_launch_cfg cfg{t, b};
+            pscl_launch_cfg cfg{t, b, 0};
             pscl_plan* p = nullptr;
             pscl_status cs = pscl_plan_create_cfg(N, K, frozen_mask, crc_poly, crc_len, L, dtype,
                                                   spc_max, mode, &cfg, &p);
@@ -2226,8 +2321,8 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
             return PSCL_E_UNSUPPORTED;
     }
     const int dtype = plans[0]->dtype;
-    int NT = 0, budget = 0;
-    default_launch(dtype, NT, budget);
+    int NT = 0, budget = 0, cap_unused = 0;
+    default_launch(dtype, NT, budget, cap_unused);
     if (cfg && cfg->threads) NT = cfg->threads;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
     int dev = 0;
@@ -2397,6 +2492,83 @@ pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const 
         if (old) pscl_group_destroy(old);
     }
     return pscl_group_decode(g, jobs, n_jobs, stream);
+}
+
+void pscl_adaptive_destroy(pscl_adaptive* ad) {
+    if (!ad) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ad->d_idx);
+    (void)hipFree(ad->d_count);
+    (void)hipFree(ad->d_next);
+    (void)hipFree(ad->d_ok);
+    delete ad;
+}
+
+pscl_status pscl_adaptive_create(const pscl_plan* fast, const pscl_plan* list, int64_t max_frames,
+                                 pscl_adaptive** out) {
+    if (!out || !fast || !list || max_frames < 1) return PSCL_E_INVALID;
+    if (fast->L != 1 || fast->N != list->N || fast->K != list->K || fast->r != list->r ||
+        fast->poly != list->poly || fast->dtype != list->dtype || fast->frozen != list->frozen ||
+        fast->device != list->device || fast->r == 0)
+        return PSCL_E_INVALID;
+    const void* kern = list->dtype == PSCL_F32   ? (const void*)&decode_gathered_kernel<float>
+                       : list->dtype == PSCL_I16 ? (const void*)&decode_gathered_kernel<int16_t>
+                                                 : (const void*)&decode_gathered_kernel<int8_t>;
+    pscl_status st = hip_status(
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, list->lds_bytes));
+    if (st != PSCL_OK) return st;
+    pscl_adaptive* ad = new pscl_adaptive();
+    ad->fast = fast;
+    ad->list = list;
+    ad->max_frames = max_frames;
+    st = hip_status(hipMalloc((void**)&ad->d_idx, sizeof(int64_t) * (size_t)max_frames));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&ad->d_count, 8));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&ad->d_next, 8));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&ad->d_ok, (size_t)max_frames));
+    if (st != PSCL_OK) {
+        pscl_adaptive_destroy(ad);
+        return st;
+    }
+    *out = ad;
+    return PSCL_OK;
+}
+
+pscl_status pscl_adaptive_decode(pscl_adaptive* ad, const void* llr, int64_t F, uint8_t* u_hat,
+                                 uint8_t* crc_ok, void* pm, int64_t* n_list, void* stream) {
+    if (!ad || F < 0 || F > ad->max_frames) return PSCL_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    if (F == 0) {
+        if (n_list) hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s,
+                                       (unsigned long long*)n_list);
+        return hipGetLastError() == hipSuccess ? PSCL_OK : PSCL_E_HIP;
+    }
+    uint8_t* ok = crc_ok ? crc_ok : ad->d_ok;
+    pscl_status st = pscl_decode(ad->fast, llr, F, u_hat, ok, pm, stream);
+    if (st != PSCL_OK) return st;
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, ad->d_count);
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, ad->d_next);
+    hipLaunchKernelGGL(gather_failed, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, ok, F,
+                       ad->d_idx, ad->d_count);
+    const pscl_plan* p = ad->list;
+    switch (p->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL(decode_gathered_kernel<float>, dim3(p->grid_max), dim3(p->NT),
+                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const float*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL(decode_gathered_kernel<int16_t>, dim3(p->grid_max), dim3(p->NT),
+                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const int16_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+        default:
+            hipLaunchKernelGGL(decode_gathered_kernel<int8_t>, dim3(p->grid_max), dim3(p->NT),
+                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const int8_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+    }
+    if (n_list) hipLaunchKernelGGL(copy_count, dim3(1), dim3(1), 0, s, ad->d_count, n_list);
+    return hipGetLastError() == hipSuccess ? PSCL_OK : PSCL_E_HIP;
 }
 
 }  // extern "C"

@@ -148,14 +148,14 @@ def test_launch_cfg_and_autotune_validate_arguments(pk):
     h = ctypes.c_void_p()
     u8 = frozen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     for threads in (32, 96, 2048, -64):
-        cfg = pk.LaunchCfg(threads, 0)
+        cfg = pk.LaunchCfg(threads, 0, 0)
         assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(cfg),
                                            ctypes.byref(h)) == 1
-    cfg = pk.LaunchCfg(64, -1)
+    cfg = pk.LaunchCfg(64, -1, 0)
     assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(cfg),
                                        ctypes.byref(h)) == 1
     assert not h.value
-    best = pk.LaunchCfg(0, 0)
+    best = pk.LaunchCfg(0, 0, 0)
     # no output, no frames, no input
     assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, None, None) == 1
     assert pk.lib.pscl_autotune(8, 4, u8, 0, 0, 4, 0, 4, 0, None, 1, None, ctypes.byref(best),
@@ -200,3 +200,12 @@ def test_server_and_replay_validate_arguments(pk):
     assert pk.lib.pscl_replay(None, None, 0, None, None, 0, None, None, None) == 1
     assert pk.lib.pscl_replay(None, plans, 1, None, None, -1, None, None, None) == 1
     assert pk.lib.pscl_replay(None, plans, 1, None, None, 2, None, None, None) == 1
+
+
+def test_adaptive_validates_arguments(pk):
+    h = ctypes.c_void_p()
+    assert pk.lib.pscl_adaptive_create(None, None, 8, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_adaptive_create(None, None, 0, ctypes.byref(h)) == 1
+    assert not h.value
+    assert pk.lib.pscl_adaptive_decode(None, None, 1, None, None, None, None, None) == 1
+    pk.lib.pscl_adaptive_destroy(None)
