@@ -189,6 +189,32 @@ def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), s
     return out
 
 
+def adaptive_leg(pk, torch, np, synth, code, b, frames, dtypes=("f32", "i8"), steps=5):
+    """Adaptive decoding (L = 1 first, L = 32 for the frames whose CRC fails)
+    on the headline frames: info Gbps and the share of frames list-decoded."""
+    out = {}
+    for dtype in dtypes:
+        host = synth.quantize(b.llr_f32, dtype)
+        llr = torch.from_numpy(host).cuda()
+        fast = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 1, dtype)
+        lst = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 32, dtype)
+        ad = pk.Adaptive(fast, lst, max_frames=frames)
+        u, ok, pm, n_list = ad.decode(llr)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ad.decode(llr, u, ok, pm, n_list)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[dtype] = {"gbps": round(frames * PAYLOAD / (ms * 1e-3) / 1e9, 4), "ms": round(ms, 3),
+                      "list_decoded": int(n_list.item()),
+                      "fer": float((u.cpu().numpy() != b.info).any(axis=1).mean())}
+        ad.close()
+    return out
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -211,6 +237,7 @@ def main():
                     help="time only --dtype (no int8, mixed or serving legs)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-decoding leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -323,7 +350,10 @@ def main():
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
 
-    mixed = serving = None
+    mixed = serving = adaptive = None
+    if not args.single and not args.no_adaptive:
+        print("[bench] adaptive decoding", file=sys.stderr, flush=True)
+        adaptive = adaptive_leg(pk, torch, np, synth, code, b, args.frames)
     if not args.single and not args.no_mixed:
         print("[bench] mixed launch vs per-code launches", file=sys.stderr, flush=True)
         mixed = mixed_leg(pk, torch, synth)
@@ -354,6 +384,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "other_dtypes": extra,
+        "adaptive": adaptive,
         "mixed": mixed,
         "serving": serving,
     }
