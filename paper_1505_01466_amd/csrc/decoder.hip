@@ -42,6 +42,11 @@ constexpr int MAXLVL = 13;  // tree levels 0..12 (N <= 4096)
 constexpr int SP_LDS = 0;   // operand in LDS
 constexpr int SP_WS = 1;    // operand in the global workspace
 constexpr int SP_CH = 2;    // operand is the channel row
+// operand is the stage below the root, recomputed from the channel row
+// (the root's F for its left child, its G with the path's left-half partial
+// sums for its right child) instead of stored
+constexpr int SP_VT = 3;
+constexpr int OP_NOP = 7;  // a record with nothing to do
 
 #define DEV __device__ __forceinline__
 
@@ -214,6 +219,7 @@ struct ChunkFG;
 
 template <>
 struct ChunkFG<float> {
+    static DEV uint4 clamp(const uint4& x) { return x; }
     // one IEEE min / max each: exact, and a zero's sign never decides
     // anything (hard decisions compare with < 0)
     static DEV uint4 f(const uint4& x, const uint4& y) {
@@ -239,6 +245,13 @@ struct ChunkFG<float> {
 
 template <>
 struct ChunkFG<int16_t> {
+    // channel values into [-32767, 32767]
+    static DEV uint32_t clamp_w(uint32_t w) {
+        return as_u32(__builtin_elementwise_max(as_s16x2(w), (s16x2)(-32767)));
+    }
+    static DEV uint4 clamp(const uint4& x) {
+        return make_uint4(clamp_w(x.x), clamp_w(x.y), clamp_w(x.z), clamp_w(x.w));
+    }
     static DEV uint4 f(const uint4& x, const uint4& y) {
         return make_uint4(f_x2(x.x, y.x), f_x2(x.y, y.y), f_x2(x.z, y.z), f_x2(x.w, y.w));
     }
@@ -266,6 +279,17 @@ struct ChunkFG<int16_t> {
 // (0x8100) completes the saturation to [-127, 127].
 template <>
 struct ChunkFG<int8_t> {
+    // channel values into [-127, 127] (via the high bytes of 16-bit halves)
+    static DEV uint32_t clamp_w(uint32_t w) {
+        const s16x2 lo = __builtin_elementwise_max(as_s16x2(__builtin_amdgcn_perm(0u, w, 0x010c000cu)),
+                                                   (s16x2)(-32512));
+        const s16x2 hi = __builtin_elementwise_max(as_s16x2(__builtin_amdgcn_perm(0u, w, 0x030c020cu)),
+                                                   (s16x2)(-32512));
+        return __builtin_amdgcn_perm(as_u32(hi), as_u32(lo), 0x07050301u);
+    }
+    static DEV uint4 clamp(const uint4& x) {
+        return make_uint4(clamp_w(x.x), clamp_w(x.y), clamp_w(x.z), clamp_w(x.w));
+    }
     static DEV uint32_t f_word(uint32_t xw, uint32_t yw) {
         const uint32_t z0 = f_x2(__builtin_amdgcn_perm(0u, xw, 0x010c000cu),
                                  __builtin_amdgcn_perm(0u, yw, 0x010c000cu));
@@ -436,6 +460,49 @@ DEV void wave_sync() {
 // F / G of one path at a level-k node, eqs. (f) and (g): lane g of the group
 // takes 16-byte chunks g, g + G, ..., up to U of them loaded before any is
 // stored.  The left partial sums of G share the output's space.
+// F / G at the level below the root reading that level's stage without
+// storing it: element j of the node's input is F(ch[j], ch[j + N/2]) for the
+// root's left child and G(ch[j], ch[j + N/2], b[j]) with the path's
+// left-half partial sums b (op.x, in the workspace) for its right child
+// (op side bit).  Same arithmetic, in the same order, as storing it.
+template <typename T, bool IS_G, int OSP>
+DEV void pp_fg_virtual(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
+    using IO = VecIO<T>;
+    constexpr int V = IO::V;
+    constexpr int LOGV = IO::LOGV;
+    const int M = 1 << (k - 1);  // outputs; the node has 2M inputs, the channel 4M
+    const bool right = op_side(op) != 0;
+    const T* ch = c.chan;
+    T* out = c.template stage<OSP>(op.y, k - 1, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.template bw<OSP>(op.z, k - 1, c.srcB(k - 1, q.p));
+    const uint32_t* br = right ? c.template bw<SP_WS>(op.x, k, c.srcB(k, q.p)) : nullptr;
+    const int nch = M >> LOGV;
+    auto bits = [&](const uint32_t* w, int e) { return w[e >> 5] >> (e & 31); };
+    for (int ch0 = q.g; ch0 < nch; ch0 += q.G) {
+        const int e = ch0 << LOGV;  // first output element of the chunk
+        // the node's inputs e.. and M + e.. from channel elements e, e + 2M,
+        // M + e, 3M + e
+        const uint4 c0 = ChunkFG<T>::clamp(*(const uint4*)(ch + e));
+        const uint4 c2 = ChunkFG<T>::clamp(*(const uint4*)(ch + 2 * M + e));
+        const uint4 c1 = ChunkFG<T>::clamp(*(const uint4*)(ch + M + e));
+        const uint4 c3 = ChunkFG<T>::clamp(*(const uint4*)(ch + 3 * M + e));
+        uint4 x, y;
+        if (right) {
+            x = ChunkFG<T>::g(c0, c2, bits(br, e));
+            y = ChunkFG<T>::g(c1, c3, bits(br, M + e));
+        } else {
+            x = ChunkFG<T>::f(c0, c2);
+            y = ChunkFG<T>::f(c1, c3);
+        }
+        uint4 r;
+        if constexpr (IS_G) r = ChunkFG<T>::g(x, y, bits(bl, e));
+        else r = ChunkFG<T>::f(x, y);
+        *(uint4*)(out + e) = r;
+    }
+    if (q.g == 0) c.setA(k - 1, q.p);
+}
+
 template <typename T, bool IS_G, int ISP, int OSP>
 DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     using IO = VecIO<T>;
@@ -446,6 +513,10 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     constexpr int U = 4;
     if (!q.valid) return;
     const int M = 1 << (k - 1);
+    if constexpr (ISP == SP_VT) {
+        pp_fg_virtual<T, IS_G, OSP>(c, op, k, q);
+        return;
+    }
     const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, q.p));
     T* out = c.template stage<OSP>(op.y, k - 1, q.p);
     const uint32_t* bl = nullptr;
@@ -510,6 +581,9 @@ DEV void pp_fg_any(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     else if (isp == SP_WS) {
         if (osp == SP_WS) pp_fg<T, IS_G, SP_WS, SP_WS>(c, op, k, q);
         else pp_fg<T, IS_G, SP_WS, SP_LDS>(c, op, k, q);
+    } else if (isp == SP_VT) {
+        if (osp == SP_WS) pp_fg<T, IS_G, SP_VT, SP_WS>(c, op, k, q);
+        else pp_fg<T, IS_G, SP_VT, SP_LDS>(c, op, k, q);
     } else {
         if (osp == SP_WS) pp_fg<T, IS_G, SP_CH, SP_WS>(c, op, k, q);
         else pp_fg<T, IS_G, SP_CH, SP_LDS>(c, op, k, q);
@@ -1577,6 +1651,8 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
             case OP_R0:
                 pp_rate0_any<T>(c, op, k, side, q);
                 break;
+            case OP_NOP:
+                break;
             default: {
                 if constexpr (std::is_same<T, float>::value) {
                     // a short forking leaf: fused in one wavefront (measured
@@ -1847,8 +1923,11 @@ struct Layout {
     int64_t ws_frame;
 };
 
+bool virtual_top(const pscl_plan* p, int k_glob);
+
 int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     const int L = p->L, n = p->n, es = elem_size(p->dtype);
+    const bool vt = virtual_top(p, k_glob);
     int off = 0;
     int64_t woff = 0;
     auto place = [&](int bytes, bool lds) {
@@ -1862,7 +1941,8 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
         return v;
     };
     for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
-    for (int k = 0; k < n; ++k) lay.a_off[k] = place(L * (1 << k) * es, k < k_glob);
+    for (int k = 0; k < n; ++k)  // the stage below the root is not stored when recomputed
+        lay.a_off[k] = (vt && k == n - 1) ? 0 : place(L * (1 << k) * es, k < k_glob);
     for (int k = 0; k <= n; ++k) {
         const int bytes = L * words_host(k) * 4;
         if (k < n) lay.bl_off[k] = place(bytes, k < k_glob);  // the root is never a left child
@@ -1893,14 +1973,50 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
 }
 
 // Operation records: the schedule with every operand offset and space.
+// The stage below the root can be recomputed instead of stored when it
+// would live in the workspace and only F / G operations read it.  For int8
+// the recomputation (four clamped channel chunks per output chunk) costs
+// more than the traffic it saves (measured), so int8 keeps storing it.
+bool virtual_top(const pscl_plan* p, int k_glob) {
+    const int n = p->n;
+    if (p->dtype == PSCL_I8) return false;
+    if (n < 3 || n - 1 < k_glob || p->sched.empty()) return false;
+    if (p->sched[0].type != OP_F || p->sched[0].k != n) return false;  // root is split
+    for (const SchedOp& s : p->sched)
+        if (s.k == n - 1 && s.type != OP_F && s.type != OP_G && s.type != OP_COMB) return false;
+    // the stage must be wide enough for whole vector chunks
+    return (1 << (n - 2)) >= 16;
+}
+
 std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glob) {
     const int n = p->n;
     auto lvl = [&](int k) { return k < k_glob ? SP_LDS : SP_WS; };
+    const bool vt = virtual_top(p, k_glob);
+    bool right_half = false;  // past the root's G
     std::vector<OpRec> out;
     for (const SchedOp& s : p->sched) {
         OpRec r{};
         const int k = s.k;
         int isp, osp;
+        if (vt && k == n && (s.type == OP_F || s.type == OP_G)) {
+            // the root's F / G: recomputed where used
+            if (s.type == OP_G) right_half = true;
+            r.meta = (uint16_t)OP_NOP;
+            out.push_back(r);
+            continue;
+        }
+        if (vt && k == n - 1 && (s.type == OP_F || s.type == OP_G)) {
+            isp = SP_VT;
+            osp = lvl(k - 1);
+            r.x = (uint16_t)lay.bl_off[n - 1];  // the root's left-half partial sums
+            r.y = (uint16_t)lay.a_off[k - 1];
+            r.z = (uint16_t)lay.bl_off[k - 1];
+            r.meta = (uint16_t)((uint32_t)s.type | ((uint32_t)k << 3) |
+                                ((uint32_t)(right_half ? 1 : 0) << 7) | ((uint32_t)isp << 12) |
+                                ((uint32_t)osp << 14));
+            out.push_back(r);
+            continue;
+        }
         if (s.type == OP_F || s.type == OP_G) {
             isp = k == n ? SP_CH : lvl(k);
             osp = lvl(k - 1);
