@@ -215,6 +215,70 @@ def adaptive_leg(pk, torch, np, synth, code, b, frames, dtypes=("f32", "i8"), st
     return out
 
 
+def spc_plus_leg(pk, torch, synth, code, b, frames, dtype="f32", lists=(8, 32), steps=3):
+    """Dec-SPC-4 (SPC nodes of 4) vs Dec-SPC-4+ (SPC nodes of any size, 4
+    least reliable bits, Sec. VII-B) on the headline frames."""
+    host = synth.quantize(b.llr_f32, dtype)
+    llr = torch.from_numpy(host).cuda()
+    out = {}
+    for L in lists:
+        row = {}
+        for name, spc_max in (("spc4", 4), ("spc4plus", code.N)):
+            plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, dtype, spc_max)
+            u, ok, pm = plan.decode(llr)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                plan.decode(llr, u, ok, pm)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            row[name] = {"gbps": round(frames * PAYLOAD / (ms * 1e-3) / 1e9, 4),
+                         "fer": float((u.cpu().numpy() != b.info).any(axis=1).mean())}
+        out[f"L{L}"] = row
+    return out
+
+
+def fer_sweep_leg(pk, torch, code, frames_per_point, points=(3.5, 3.75, 4.0, 4.25, 4.5),
+                  dtypes=("f32", "i8"), chunk=65536, seed=0x46455253):
+    """Frame error rate of the L = 32 decoder over Eb/N0, with frames made on
+    the device (Philox payloads and noise, see pscl_generate) chunk by chunk:
+    frame errors counted against the generated information bits."""
+    out = {}
+    for dtype in dtypes:
+        gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, dtype)
+        plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 32, dtype)
+        llr, info = gen.generate(chunk, points[0], seed)
+        u, ok, pm = plan.decode(llr)
+        rows = {}
+        gen_ms = dec_ms = 0.0
+        for e in points:
+            errs = 0
+            done = 0
+            while done < frames_per_point:
+                F = min(chunk, frames_per_point - done)
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record()
+                gen.generate(F, e, seed, first_frame=done, llr=llr[:F], info=info[:F])
+                e1.record()
+                plan.decode(llr[:F], u[:F], ok[:F], pm[:F])
+                e2.record()
+                errs += int((u[:F] != info[:F]).any(dim=1).sum().item())
+                gen_ms += e0.elapsed_time(e1)
+                dec_ms += e1.elapsed_time(e2)
+                done += F
+            lo, hi = wilson(errs, done)
+            rows[str(e)] = {"frames": done, "errors": errs, "fer": errs / done,
+                            "ci95": [round(lo, 8), round(hi, 8)]}
+        n_all = frames_per_point * len(points)
+        out[dtype] = {"points": rows, "generator_frames_per_s": round(n_all / (gen_ms * 1e-3)),
+                      "decoder_frames_per_s": round(n_all / (dec_ms * 1e-3))}
+        gen.close()
+        plan.close()
+    return out
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -238,6 +302,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-decoding leg")
+    ap.add_argument("--no-spc-plus", action="store_true", help="skip the SPC-4 vs SPC-4+ leg")
+    ap.add_argument("--no-fer-sweep", action="store_true", help="skip the FER sweep leg")
+    ap.add_argument("--sweep-frames", type=int, default=1 << 20,
+                    help="frames per Eb/N0 point of the FER sweep (made on the device)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -350,7 +418,14 @@ def main():
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
 
-    mixed = serving = adaptive = None
+    mixed = serving = adaptive = spc_plus = sweep = None
+    if not args.single and not args.no_fer_sweep:
+        print(f"[bench] FER sweep, {args.sweep_frames} device-made frames per point",
+              file=sys.stderr, flush=True)
+        sweep = fer_sweep_leg(pk, torch, code, args.sweep_frames)
+    if not args.single and not args.no_spc_plus:
+        print("[bench] SPC-4 vs SPC-4+", file=sys.stderr, flush=True)
+        spc_plus = spc_plus_leg(pk, torch, synth, code, b, args.frames)
     if not args.single and not args.no_adaptive:
         print("[bench] adaptive decoding", file=sys.stderr, flush=True)
         adaptive = adaptive_leg(pk, torch, np, synth, code, b, args.frames)
@@ -385,6 +460,8 @@ def main():
         "cpu_baseline": cpu,
         "other_dtypes": extra,
         "adaptive": adaptive,
+        "spc4_vs_spc4plus": spc_plus,
+        "fer_sweep": sweep,
         "mixed": mixed,
         "serving": serving,
     }

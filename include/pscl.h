@@ -339,6 +339,28 @@ void pscl_adaptive_destroy(pscl_adaptive* ad);
 pscl_status pscl_adaptive_decode(pscl_adaptive* ad, const void* llr, int64_t F, uint8_t* u_hat,
                                  uint8_t* crc_ok, void* pm, int64_t* n_list, void* stream);
 
+/*
+ * Synthetic frames on the device, the workload of Sec. VII-A: uniform
+ * payload bits, the CRC appended inside K (conventions above), polar
+ * encoding x = u F^{(x)n}, BPSK s = 1 - 2x over AWGN y = s + sigma n with
+ * sigma^2 = 1 / (2 R 10^(EbN0/10)), R = (K - r) / N, LLR = 2y / sigma^2,
+ * quantised for the integer dtypes (int8: rne(4 LLR) clipped to +-127;
+ * int16: rne(64 LLR) clipped to +-32767).  Random numbers: Philox4x32-10
+ * keyed by the seed, counters by frame index, so frame f is the same
+ * whatever call produces it; normals by Box-Muller.  For throughput and
+ * error-rate runs at scale.
+ */
+typedef struct pscl_generator pscl_generator;
+pscl_status pscl_generator_create(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
+                                  int crc_len, int dtype, pscl_generator** out);
+void pscl_generator_destroy(pscl_generator* gen);
+
+/* Frames first_frame .. first_frame + F - 1 into llr (device, F x N in the
+ * dtype) and, when not NULL, their K information bits into info (device,
+ * F x K bytes: payload then CRC), asynchronously on the stream. */
+pscl_status pscl_generate(pscl_generator* gen, uint64_t seed, int64_t first_frame, int64_t F,
+                          double ebn0_db, void* llr, uint8_t* info, void* stream);
+
 /* Launch shape chosen for a plan: frames per workgroup, threads per
  * workgroup, workgroups, LDS bytes per workgroup, bytes of global workspace,
  * first tree level whose LLR stage lives in global memory (n = none). */

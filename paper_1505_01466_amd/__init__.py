@@ -8,6 +8,7 @@ The decoder is the C-ABI library ``_lib/libpscl.so`` (declared in
 from ._binding import (  # noqa: F401
     DTYPES,
     Adaptive,
+    Generator,
     LIB_PATH,
     Group,
     Job,

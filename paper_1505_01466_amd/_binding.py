@@ -129,6 +129,13 @@ def _load():
     lib.pscl_adaptive_destroy.restype = None
     lib.pscl_adaptive_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp, vp]
     lib.pscl_adaptive_decode.restype = c_int
+    lib.pscl_generator_create.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int,
+                                          ctypes.POINTER(vp)]
+    lib.pscl_generator_create.restype = c_int
+    lib.pscl_generator_destroy.argtypes = [vp]
+    lib.pscl_generator_destroy.restype = None
+    lib.pscl_generate.argtypes = [vp, c_u64, c_i64, c_i64, ctypes.c_double, vp, vp, vp]
+    lib.pscl_generate.restype = c_int
     return lib
 
 
@@ -456,6 +463,49 @@ class Adaptive:
     def close(self):
         if getattr(self, "_h", None):
             lib.pscl_adaptive_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Generator:
+    """Synthetic frames on the device (see pscl_generator_create)."""
+
+    def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, dtype: str = "f32"):
+        import torch
+
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        self.N, self.K, self.dtype = N, K, dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        fz = _mask(frozen)
+        h = ctypes.c_void_p(None)
+        _check(lib.pscl_generator_create(N, K, _u8p(fz), crc_poly, crc_len, DTYPES[dtype],
+                                         ctypes.byref(h)), "pscl_generator_create")
+        self._h = h
+
+    def generate(self, F: int, ebn0_db: float, seed: int, first_frame: int = 0, llr=None,
+                 info=None, want_info: bool = True):
+        """-> (llr F x N in the dtype, info F x K uint8 or None)."""
+        import torch
+
+        want = {"f32": torch.float32, "i16": torch.int16, "i8": torch.int8}[self.dtype]
+        if llr is None:
+            llr = torch.empty((F, self.N), dtype=want, device=self.device)
+        if info is None and want_info:
+            info = torch.empty((F, self.K), dtype=torch.uint8, device=self.device)
+        _check(lib.pscl_generate(self._h, seed, first_frame, F, ebn0_db, llr.data_ptr(),
+                                 info.data_ptr() if info is not None else None,
+                                 _stream_handle(self.device)), "pscl_generate")
+        return llr, info
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pscl_generator_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libpscl.so")
 SOURCES = [os.path.join(CSRC, "decoder.hip"), os.path.join(CSRC, "schedule.cpp"),
-           os.path.join(CSRC, "server.cpp")]
+           os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "generate.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -209,3 +209,18 @@ def test_adaptive_validates_arguments(pk):
     assert not h.value
     assert pk.lib.pscl_adaptive_decode(None, None, 1, None, None, None, None, None) == 1
     pk.lib.pscl_adaptive_destroy(None)
+
+
+def test_generator_validates_arguments(pk):
+    h = ctypes.c_void_p()
+    fz = np.ones(8, np.uint8)
+    fz[[3, 5, 6, 7]] = 0
+    p = fz.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert pk.lib.pscl_generator_create(8, 4, None, 0x7, 3, 0, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_generator_create(12, 4, p, 0x7, 3, 0, ctypes.byref(h)) == 1  # N not 2^n
+    assert pk.lib.pscl_generator_create(8, 5, p, 0x7, 3, 0, ctypes.byref(h)) == 1  # K != unfrozen
+    assert pk.lib.pscl_generator_create(8, 4, p, 0x7, 4, 0, ctypes.byref(h)) == 1  # r >= K
+    assert pk.lib.pscl_generator_create(8, 4, p, 0x7, 3, 9, ctypes.byref(h)) == 1  # dtype
+    assert not h.value
+    assert pk.lib.pscl_generate(None, 1, 0, 1, 4.0, None, None, None) == 1
+    pk.lib.pscl_generator_destroy(None)

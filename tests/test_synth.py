@@ -67,3 +67,64 @@ def test_awgn_statistics():
     noise = y - s
     assert abs(noise.mean()) < 0.01
     assert abs(noise.var() / sigma2 - 1) < 0.02
+
+
+# Known-answer vectors published with Philox4x32-10 (Salmon et al., SC 2011,
+# distributed with their Random123 library): (counter, key) -> output.
+PHILOX_KAT = [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+def test_philox_known_answers():
+    from synth.philox import philox4x32_10
+
+    for ctr, key, want in PHILOX_KAT:
+        got = philox4x32_10(np.array([ctr], dtype=np.uint32), key)[0]
+        assert tuple(int(v) for v in got) == want
+
+
+def test_philox_frames_are_valid_codewords_and_independent_of_chunking():
+    from synth.philox import philox_batch
+
+    code = synth.make_code(1024, 512, 8, synth.CRC8_POLY, 2.5)
+    b = philox_batch(code, 40, 2.0, seed=0x1234_5678_9ABC, first=3)
+    assert (synth.crc_remainder(b.info[:, :code.payload], code.poly, code.r) == b.info[:, code.payload:]).all()
+    u = np.zeros((b.F, code.N), np.uint8)
+    u[:, code.info_pos] = b.info
+    assert (synth.encode(u) == b.x).all()
+    # frame f depends only on (seed, f)
+    c = philox_batch(code, 10, 2.0, seed=0x1234_5678_9ABC, first=13)
+    assert (c.info == b.info[10:20]).all() and (c.llr_f32 == b.llr_f32[10:20]).all()
+    # frame index beyond 32 bits, other seed: different bits
+    d = philox_batch(code, 10, 2.0, seed=0x1234_5678_9ABC, first=13 + (1 << 32))
+    e = philox_batch(code, 10, 2.0, seed=0x1234_5678_9ABD, first=13)
+    assert (d.info != c.info).any() and (e.info != c.info).any()
+    # integer dtypes quantise the same float32 LLRs
+    q = philox_batch(code, 40, 2.0, seed=0x1234_5678_9ABC, first=3, dtype="i8")
+    assert (q.llr == synth.quantize(b.llr_f32, "i8")).all()
+
+
+def test_philox_channel_statistics():
+    """Payload bits fair and uncorrelated; the noise recovered from the LLRs
+    is standard normal (mean, variance, tail mass, kurtosis)."""
+    from synth.philox import channel_params, philox_batch
+
+    code = synth.make_code(2048, 1723, 32, synth.CRC32_POLY, 4.0)
+    b = philox_batch(code, 200, 3.0, seed=99)
+    p = b.info[:, :code.payload].astype(np.float64)
+    assert abs(p.mean() - 0.5) < 0.005
+    assert abs(np.corrcoef(p[:, :-1].ravel(), p[:, 1:].ravel())[0, 1]) < 0.01
+    sigma, scale = channel_params(code, 3.0)
+    s = 1.0 - 2.0 * b.x.astype(np.float64)
+    n = (b.llr_f32.astype(np.float64) / float(scale) - s) / float(sigma)
+    assert abs(n.mean()) < 0.01 and abs(n.var() - 1.0) < 0.01
+    assert abs(np.mean(np.abs(n) > 2.0) - 0.0455) < 0.002
+    assert abs(np.mean(n ** 4) - 3.0) < 0.05
+    # the four Box-Muller outputs of one block are uncorrelated
+    blk = n.reshape(-1, 4)
+    cc = np.corrcoef(blk.T)
+    assert np.abs(cc - np.eye(4)).max() < 0.01
