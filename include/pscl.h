@@ -97,7 +97,7 @@ int pscl_version(void);
  *   *n_ops: number of operations (written even when cap is too small, in
  *   which case PSCL_E_INVALID is returned).
  * spc_max: largest SPC node (4 = Dec-SPC-4; up to N allowed; values below 4
- * disable SPC nodes).  L: list size in {1, 2, 4, 8, 16, 32}.
+ * disable SPC nodes).  L: list size in {1, 2, 4, ..., 128}.
  */
 pscl_status pscl_schedule(int N, const uint8_t* frozen_mask, int L, int spc_max,
                           int mode, int32_t* ops, int cap, int* n_ops);
@@ -106,7 +106,8 @@ pscl_status pscl_schedule(int N, const uint8_t* frozen_mask, int L, int spc_max,
  * Create a decoding plan on the current HIP device.
  *   N: power of two in [2, 4096].  K: number of unfrozen positions (1..N).
  *   crc_poly, crc_len: see the conventions above (crc_len <= K).
- *   L: list size in {1, 2, 4, 8, 16, 32}.  dtype: pscl_dtype.
+ *   L: list size in {1, 2, 4, 8, 16, 32, 64, 128} (Sec. VII-B uses 128 for
+ *   the CRC-length comparison).  dtype: pscl_dtype.
  *   spc_max, mode: see pscl_schedule.
  * Allocates the device schedule, CRC tables and decoding workspace.
  * Returns PSCL_E_INVALID on bad arguments, PSCL_E_NODEV without a gfx950
@@ -120,11 +121,13 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
 /*
  * Launch shape of a plan.  A zero field takes the library default for the
  * dtype (float32: 128 threads, 24 KiB; int16: 64 threads, 12 KiB; int8: 64
- * threads, 10 KiB, chosen by measurement at (2048,1723) L=32), which the
+ * threads, 10 KiB, chosen by measurement at (2048,1723) L=32; above L = 32
+ * the budget scales by L / 32 and the threads rise to at least L), which the
  * environment variables PSCL_THREADS, PSCL_LDS_BUDGET and
  * PSCL_MAX_WG_PER_CU override.
  *   threads: threads per workgroup (one frame per workgroup): 64, 128, 256,
- *            512 or 1024.
+ *            512 or 1024; at least 128 for L = 128 (one wavefront serves at
+ *            most 64 paths), else PSCL_E_UNSUPPORTED.
  *   lds_budget: LDS bytes per workgroup (one frame) for the path tables, candidate
  *            scratch and the low tree levels' LLR stages and partial sums;
  *            the levels that do not fit go to the global workspace.  A

@@ -468,7 +468,6 @@ DEV void wave_sync() {
 template <typename T, bool IS_G, int OSP>
 DEV void pp_fg_virtual(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     using IO = VecIO<T>;
-    constexpr int V = IO::V;
     constexpr int LOGV = IO::LOGV;
     const int M = 1 << (k - 1);  // outputs; the node has 2M inputs, the channel 4M
     const bool right = op_side(op) != 0;
@@ -1080,7 +1079,7 @@ DEV void bitonic_select(const uint64_t* ck, uint64_t* skey, int lane, int C, int
 // candidate below T0 is dropped before sorting.  The candidates that remain
 // are compacted (wavefront ballots) and sorted; ties cannot occur since keys
 // carry the enumeration index.
-template <typename T>
+template <typename T, bool WIDE>
 DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
     if (c.tid >= 64) return;
     const int lane = c.lane;
@@ -1091,7 +1090,13 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
     }
     uint64_t t0 = 0ull;
     if (P == L) {
-        uint64_t v = lane < P ? ck[lane << lc] : ~0ull;
+        uint64_t v;
+        if constexpr (WIDE) {
+            v = ~0ull;
+            for (int s = lane; s < P; s += 64) v = umin64(v, ck[s << lc]);
+        } else {
+            v = lane < P ? ck[lane << lc] : ~0ull;
+        }
         xor_steps(64, [&](auto mc) {
             uint64_t pa, pb;
             xpair64<decltype(mc)::value>(v, pa, pb);
@@ -1113,9 +1118,35 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
         n += (int)__builtin_popcountll(bal);
     }
     wave_sync();
-    if (n <= 64) bitonic_select<1>(kept, c.skey(), lane, n, L);
-    else if (n <= 128) bitonic_select<2>(kept, c.skey(), lane, n, L);
-    else bitonic_select<4>(kept, c.skey(), lane, n, L);
+    if constexpr (WIDE) {
+        // More than 256 left (L = 64 or 128 only): the best L of each chunk of
+        // 256 are kept, chunk c's at [c L, c L + L), until 256 or fewer remain;
+        // the overall best L are among them.  A chunk's keys are in registers
+        // before any of its results are written, and those writes land below
+        // the chunk's end.  One call site per network width keeps the code
+        // small.
+        for (;;) {
+            const bool last = n <= 256;
+            int m = 0;
+            for (int base = 0; base < n; base += 256) {
+                const int cn = last ? n : (n - base < 256 ? n - base : 256);
+                const int keep = last ? L : (cn < L ? cn : L);
+                uint64_t* dst = last ? c.skey() : kept + m;
+                if (cn <= 64) bitonic_select<1>(kept + base, dst, lane, cn, keep);
+                else if (cn <= 128) bitonic_select<2>(kept + base, dst, lane, cn, keep);
+                else bitonic_select<4>(kept + base, dst, lane, cn, keep);
+                wave_sync();
+                m += keep;
+                if (last) break;
+            }
+            if (last) break;
+            n = m;
+        }
+    } else {
+        if (n <= 64) bitonic_select<1>(kept, c.skey(), lane, n, L);
+        else if (n <= 128) bitonic_select<2>(kept, c.skey(), lane, n, L);
+        else bitonic_select<4>(kept, c.skey(), lane, n, L);
+    }
 }
 
 // Pass 3 of a forking leaf for one destination slot j: its metric, its path
@@ -1455,7 +1486,7 @@ DEV uint64_t word_syndrome(uint32_t v, const uint64_t* sy, int nb) {
     return acc;
 }
 
-template <typename T, int RSP>
+template <typename T, int RSP, bool WIDE>
 DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_hat,
                 uint8_t* crc_ok, void* pm_out) {
     using D = Dom<T>;
@@ -1472,8 +1503,18 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
     // to the lower slot).  If the best-metric path passes, that is it;
     // only otherwise is every path's syndrome needed.
     if (c.tid < 64) {
-        const int j = c.lane < P ? c.lane : 0;
-        uint64_t key = ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+        // one lane per path; lists above 64 give a lane two paths
+        uint64_t key;
+        if constexpr (WIDE) {
+            auto path_key = [&](int j) {
+                return ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+            };
+            key = path_key(c.lane < P ? c.lane : 0);
+            if (P > 64) key = umax64(key, path_key(c.lane + 64 < P ? c.lane + 64 : 0));
+        } else {
+            const int j = c.lane < P ? c.lane : 0;
+            key = ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+        }
         xor_steps(P, [&](auto mc) {
             uint64_t pa, pb;
             xpair64<decltype(mc)::value>(key, pa, pb);
@@ -1527,10 +1568,20 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
             __syncthreads();
             // pick: one lane per path
             if (c.tid < 64) {
-                const int j = c.lane < P ? c.lane : 0;
-                const uint64_t pass = c.surv()[j] & 1;
-                uint64_t key =
-                    (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+                uint64_t key;
+                if constexpr (WIDE) {
+                    auto path_key = [&](int j) {
+                        const uint64_t pass = c.surv()[j] & 1;
+                        return (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) |
+                               (uint64_t)(255 - j);
+                    };
+                    key = path_key(c.lane < P ? c.lane : 0);
+                    if (P > 64) key = umax64(key, path_key(c.lane + 64 < P ? c.lane + 64 : 0));
+                } else {
+                    const int j = c.lane < P ? c.lane : 0;
+                    const uint64_t pass = c.surv()[j] & 1;
+                    key = (pass << 40) | ((uint64_t)D::order(c.pm()[j]) << 8) | (uint64_t)(255 - j);
+                }
                 xor_steps(P, [&](auto mc) {
                     uint64_t pa, pb;
                     xpair64<decltype(mc)::value>(key, pa, pb);
@@ -1605,7 +1656,7 @@ DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
 // Schedule records are read with scalar loads (sched points into a
 // read-only kernel argument), the next one while the current operation
 // runs.  Outputs go to entry f of u_hat / crc_ok / pm_out.
-template <typename T>
+template <typename T, bool WIDE>
 DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sched, int64_t f,
                       uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                       void* __restrict__ pm_out) {
@@ -1654,10 +1705,10 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
             case OP_NOP:
                 break;
             default: {
-                if constexpr (std::is_same<T, float>::value) {
+                if constexpr (std::is_same<T, float>::value && !WIDE) {
                     // a short forking leaf: fused in one wavefront (measured
                     // faster for float32 only, whose workgroups span two
-                    // wavefronts)
+                    // wavefronts; its networks hold at most 32 paths)
                     if (k <= 5) {
                         P = fork_small<T>(c, op, type, k, side, cc, P);
                         q = make_grp(c.tid, c.NT, P);
@@ -1674,7 +1725,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                 pprune = C > c.L;
                 __syncthreads();
                 if (pprune) {
-                    select_rank<T>(c, C, c.L, P, ilog2u(cc));
+                    select_rank<T, WIDE>(c, C, c.L, P, ilog2u(cc));
                     __syncthreads();
                 }
                 P = pprune ? c.L : C;
@@ -1688,8 +1739,8 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
     }
     if (pend) pp_emit_pending<T>(c, pop, pprune, q);
     __syncthreads();
-    if (a.root_sp == SP_LDS) finish<T, SP_LDS>(c, a, P, f, u_hat, crc_ok, pm_out);
-    else finish<T, SP_WS>(c, a, P, f, u_hat, crc_ok, pm_out);
+    if (a.root_sp == SP_LDS) finish<T, SP_LDS, WIDE>(c, a, P, f, u_hat, crc_ok, pm_out);
+    else finish<T, SP_WS, WIDE>(c, a, P, f, u_hat, crc_ok, pm_out);
     __syncthreads();
 }
 
@@ -1713,7 +1764,7 @@ struct WorkCounter {
 };
 
 // One code: frames taken from the counter, any workgroup any frame.
-template <typename T>
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(1024)
     decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
                   uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
@@ -1731,7 +1782,7 @@ __global__ void __launch_bounds__(1024)
         const int64_t f = wc.next(c.tid, slot);
         if (f >= F) break;
         c.chan = llr + f * a.N;
-        decode_frame(c, a, sched, f, u_hat, crc_ok, pm_out);
+        decode_frame<T, WIDE>(c, a, sched, f, u_hat, crc_ok, pm_out);
     }
 }
 
@@ -1754,7 +1805,7 @@ struct DevJob {
 // Frames are handed out one at a time from a counter (vector atomics), so
 // that frames of very different cost balance across workgroups; every
 // workgroup leaves once the counter has passed the last frame.
-template <typename T>
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(1024)
     decode_mixed_kernel(const DevPlan* __restrict__ plans, const DevJob* __restrict__ jobs,
                         int n_jobs, int64_t total, const uint64_t* __restrict__ sched,
@@ -1784,7 +1835,7 @@ __global__ void __launch_bounds__(1024)
         const int64_t f = g - J.base;
         bind_plan(c, a, wsb);
         c.chan = (const T*)J.llr + f * a.N;
-        decode_frame(c, a, sched + D.op_base, f, J.u_hat, J.crc_ok, J.pm);
+        decode_frame<T, WIDE>(c, a, sched + D.op_base, f, J.u_hat, J.crc_ok, J.pm);
     }
 }
 
@@ -1803,7 +1854,7 @@ __global__ void gather_failed(const uint8_t* __restrict__ crc_ok, int64_t F,
 }
 
 // The gathered frames, each written back at its own index.
-template <typename T>
+template <typename T, bool WIDE>
 __global__ void __launch_bounds__(1024)
     decode_gathered_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr,
                            const int64_t* __restrict__ idx,
@@ -1825,7 +1876,7 @@ __global__ void __launch_bounds__(1024)
         if (i >= n) break;
         const int64_t f = idx[i];
         c.chan = llr + f * a.N;
-        decode_frame(c, a, sched, f, u_hat, crc_ok, pm_out);
+        decode_frame<T, WIDE>(c, a, sched, f, u_hat, crc_ok, pm_out);
     }
 }
 
@@ -1874,6 +1925,7 @@ struct pscl_adaptive {
 
 struct pscl_group {
     int device = 0, dtype = 0, NT = 64, lds_bytes = 0, grid = 0, max_jobs = 0;
+    bool wide = false;  // some plan's list is above 32 paths
     int slots = 0;  // calls in flight
     int64_t ws_frame = 0;
     std::vector<const pscl_plan*> plans;
@@ -1891,6 +1943,64 @@ struct pscl_group {
     std::mutex mu;
 };
 
+template <bool W>
+const void* mixed_kernel_for(int dtype) {
+    return dtype == PSCL_F32   ? (const void*)&decode_mixed_kernel<float, W>
+           : dtype == PSCL_I16 ? (const void*)&decode_mixed_kernel<int16_t, W>
+                               : (const void*)&decode_mixed_kernel<int8_t, W>;
+}
+
+template <bool W>
+void launch_mixed(const pscl_group* g, int slot, int grid, int nj, int64_t total, hipStream_t s) {
+    switch (g->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL((decode_mixed_kernel<float, W>), dim3(grid), dim3(g->NT),
+                               g->lds_bytes, s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched,
+                               g->d_ws[slot], g->ws_frame, g->d_counter[slot]);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL((decode_mixed_kernel<int16_t, W>), dim3(grid), dim3(g->NT),
+                               g->lds_bytes, s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched,
+                               g->d_ws[slot], g->ws_frame, g->d_counter[slot]);
+            break;
+        default:
+            hipLaunchKernelGGL((decode_mixed_kernel<int8_t, W>), dim3(grid), dim3(g->NT),
+                               g->lds_bytes, s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched,
+                               g->d_ws[slot], g->ws_frame, g->d_counter[slot]);
+            break;
+    }
+}
+
+template <bool W>
+const void* gathered_kernel_for(int dtype) {
+    return dtype == PSCL_F32   ? (const void*)&decode_gathered_kernel<float, W>
+           : dtype == PSCL_I16 ? (const void*)&decode_gathered_kernel<int16_t, W>
+                               : (const void*)&decode_gathered_kernel<int8_t, W>;
+}
+
+template <bool W>
+void launch_gathered(const pscl_adaptive* ad, const void* llr, uint8_t* u_hat, uint8_t* ok,
+                     void* pm, hipStream_t s) {
+    const pscl_plan* p = ad->list;
+    switch (p->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL((decode_gathered_kernel<float, W>), dim3(p->grid_max), dim3(p->NT),
+                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const float*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL((decode_gathered_kernel<int16_t, W>), dim3(p->grid_max),
+                               dim3(p->NT), p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const int16_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+        default:
+            hipLaunchKernelGGL((decode_gathered_kernel<int8_t, W>), dim3(p->grid_max), dim3(p->NT),
+                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
+                               (const int8_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
+            break;
+    }
+}
+
 namespace {
 
 pscl_status hip_status(hipError_t e) {
@@ -1899,16 +2009,49 @@ pscl_status hip_status(hipError_t e) {
     return PSCL_E_HIP;
 }
 
-bool valid_L(int L) { return L == 1 || L == 2 || L == 4 || L == 8 || L == 16 || L == 32; }
+bool valid_L(int L) {
+    return L == 1 || L == 2 || L == 4 || L == 8 || L == 16 || L == 32 || L == 64 || L == 128;
+}
 
-const void* kernel_for(int dtype) {
+// Lists above 32 paths run a separate instance of each kernel (selection
+// over more than 256 candidates, more than 64 paths in the final pick, no
+// fused short forks), so that the code of the smaller lists is unchanged.
+bool wide_list(int L) { return L > 32; }
+
+template <bool W>
+const void* kernel_for_t(int dtype) {
     switch (dtype) {
         case PSCL_F32:
-            return (const void*)&decode_kernel<float>;
+            return (const void*)&decode_kernel<float, W>;
         case PSCL_I16:
-            return (const void*)&decode_kernel<int16_t>;
+            return (const void*)&decode_kernel<int16_t, W>;
         default:
-            return (const void*)&decode_kernel<int8_t>;
+            return (const void*)&decode_kernel<int8_t, W>;
+    }
+}
+const void* kernel_for(int dtype, int L) {
+    return wide_list(L) ? kernel_for_t<true>(dtype) : kernel_for_t<false>(dtype);
+}
+
+template <bool W>
+void launch_decode(const pscl_plan* p, int grid, hipStream_t s, const void* llr, int64_t F,
+                   uint8_t* u_hat, uint8_t* crc_ok, void* pm) {
+    switch (p->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL((decode_kernel<float, W>), dim3(grid), dim3(p->NT), p->lds_bytes, s,
+                               p->args, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat,
+                               crc_ok, pm, p->d_counter);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL((decode_kernel<int16_t, W>), dim3(grid), dim3(p->NT), p->lds_bytes,
+                               s, p->args, (const uint64_t*)p->d_ops, (const int16_t*)llr, F,
+                               u_hat, crc_ok, pm, p->d_counter);
+            break;
+        default:
+            hipLaunchKernelGGL((decode_kernel<int8_t, W>), dim3(grid), dim3(p->NT), p->lds_bytes,
+                               s, p->args, (const uint64_t*)p->d_ops, (const int8_t*)llr, F,
+                               u_hat, crc_ok, pm, p->d_counter);
+            break;
     }
 }
 
@@ -2151,11 +2294,16 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (mode != PSCL_MODE_TREE && mode != PSCL_MODE_SCL_LEAVES) return PSCL_E_INVALID;
     int NT = 0, budget = 0, wg_cap = 0;
     default_launch(dtype, NT, budget, wg_cap);
+    // lists above 32: the path tables and candidate scratch grow with L, so
+    // the default budget does too; one wavefront serves at most 64 paths
+    if (L > 32 && !getenv("PSCL_LDS_BUDGET")) budget *= L / 32;
+    if (NT < L && !getenv("PSCL_THREADS")) NT = L;
     if (cfg && cfg->threads) NT = cfg->threads;
     if (cfg && cfg->lds_budget) budget = cfg->lds_budget;
     if (cfg && cfg->max_wg_per_cu) wg_cap = cfg->max_wg_per_cu;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
     if (budget < 0 || wg_cap < 0) return PSCL_E_INVALID;
+    if (NT < L && L > 64) return PSCL_E_UNSUPPORTED;
     int kk = 0;
     for (int i = 0; i < N; ++i) kk += frozen_mask[i] ? 0 : 1;
     if (kk != K || K < 1 || crc_len < 0 || crc_len > 64 || crc_len > K) return PSCL_E_INVALID;
@@ -2216,7 +2364,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     const int64_t wsf = lay.ws_frame;
     p->lds_bytes = bytes + sched_need;
     p->NT = NT;
-    p->kernel = kernel_for(dtype);
+    p->kernel = kernel_for(dtype, L);
 
     hipError_t e = hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        p->lds_bytes);
@@ -2297,23 +2445,8 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     // the frame counter starts at zero (a one-thread kernel, so that the
     // call can be captured in a graph)
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, p->d_counter);
-    switch (p->dtype) {
-        case PSCL_F32:
-            hipLaunchKernelGGL(decode_kernel<float>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat,
-                               crc_ok, pm, p->d_counter);
-            break;
-        case PSCL_I16:
-            hipLaunchKernelGGL(decode_kernel<int16_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const uint64_t*)p->d_ops, (const int16_t*)llr, F, u_hat,
-                               crc_ok, pm, p->d_counter);
-            break;
-        default:
-            hipLaunchKernelGGL(decode_kernel<int8_t>, dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const uint64_t*)p->d_ops, (const int8_t*)llr, F, u_hat,
-                               crc_ok, pm, p->d_counter);
-            break;
-    }
+    if (wide_list(p->L)) launch_decode<true>(p, grid, s, llr, F, u_hat, crc_ok, pm);
+    else launch_decode<false>(p, grid, s, llr, F, u_hat, crc_ok, pm);
     e = hipGetLastError();
     return e == hipSuccess ? PSCL_OK : PSCL_E_HIP;
 }
@@ -2437,10 +2570,13 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
             return PSCL_E_UNSUPPORTED;
     }
     const int dtype = plans[0]->dtype;
-    int NT = 0, budget = 0, cap_unused = 0;
+    int NT = 0, budget = 0, cap_unused = 0, max_L = 1;
     default_launch(dtype, NT, budget, cap_unused);
+    for (int i = 0; i < n_plans; ++i) max_L = std::max(max_L, plans[i]->L);
+    if (NT < max_L && !getenv("PSCL_THREADS")) NT = max_L;  // at most 64 paths per wavefront
     if (cfg && cfg->threads) NT = cfg->threads;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
+    if (NT < max_L && max_L > 64) return PSCL_E_UNSUPPORTED;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
     if (dev != plans[0]->device) return PSCL_E_INVALID;
@@ -2468,9 +2604,8 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
         g->ws_frame = std::max<int64_t>(g->ws_frame, p->args.ws_frame);
         n_rec += p->args.n_ops;
     }
-    const void* kern = dtype == PSCL_F32   ? (const void*)&decode_mixed_kernel<float>
-                       : dtype == PSCL_I16 ? (const void*)&decode_mixed_kernel<int16_t>
-                                           : (const void*)&decode_mixed_kernel<int8_t>;
+    g->wide = wide_list(max_L);
+    const void* kern = g->wide ? mixed_kernel_for<true>(dtype) : mixed_kernel_for<false>(dtype);
     pscl_status st = hip_status(
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, g->lds_bytes));
     int occ = 0;
@@ -2558,23 +2693,8 @@ pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, v
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, g->d_counter[slot]);
     const int grid = (int)std::min<int64_t>(total, g->grid);
     const int nj = (int)idx.size();
-    switch (g->dtype) {
-        case PSCL_F32:
-            hipLaunchKernelGGL(decode_mixed_kernel<float>, dim3(grid), dim3(g->NT), g->lds_bytes, s,
-                               g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
-                               g->ws_frame, g->d_counter[slot]);
-            break;
-        case PSCL_I16:
-            hipLaunchKernelGGL(decode_mixed_kernel<int16_t>, dim3(grid), dim3(g->NT), g->lds_bytes,
-                               s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
-                               g->ws_frame, g->d_counter[slot]);
-            break;
-        default:
-            hipLaunchKernelGGL(decode_mixed_kernel<int8_t>, dim3(grid), dim3(g->NT), g->lds_bytes,
-                               s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched, g->d_ws[slot],
-                               g->ws_frame, g->d_counter[slot]);
-            break;
-    }
+    if (g->wide) launch_mixed<true>(g, slot, grid, nj, total, s);
+    else launch_mixed<false>(g, slot, grid, nj, total, s);
     e = hipGetLastError();
     if (e != hipSuccess) return PSCL_E_HIP;
     e = hipEventRecord(g->ev[slot], s);
@@ -2627,9 +2747,8 @@ pscl_status pscl_adaptive_create(const pscl_plan* fast, const pscl_plan* list, i
         fast->poly != list->poly || fast->dtype != list->dtype || fast->frozen != list->frozen ||
         fast->device != list->device || fast->r == 0)
         return PSCL_E_INVALID;
-    const void* kern = list->dtype == PSCL_F32   ? (const void*)&decode_gathered_kernel<float>
-                       : list->dtype == PSCL_I16 ? (const void*)&decode_gathered_kernel<int16_t>
-                                                 : (const void*)&decode_gathered_kernel<int8_t>;
+    const void* kern = wide_list(list->L) ? gathered_kernel_for<true>(list->dtype)
+                                          : gathered_kernel_for<false>(list->dtype);
     pscl_status st = hip_status(
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, list->lds_bytes));
     if (st != PSCL_OK) return st;
@@ -2666,23 +2785,8 @@ pscl_status pscl_adaptive_decode(pscl_adaptive* ad, const void* llr, int64_t F, 
     hipLaunchKernelGGL(gather_failed, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, s, ok, F,
                        ad->d_idx, ad->d_count);
     const pscl_plan* p = ad->list;
-    switch (p->dtype) {
-        case PSCL_F32:
-            hipLaunchKernelGGL(decode_gathered_kernel<float>, dim3(p->grid_max), dim3(p->NT),
-                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
-                               (const float*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
-            break;
-        case PSCL_I16:
-            hipLaunchKernelGGL(decode_gathered_kernel<int16_t>, dim3(p->grid_max), dim3(p->NT),
-                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
-                               (const int16_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
-            break;
-        default:
-            hipLaunchKernelGGL(decode_gathered_kernel<int8_t>, dim3(p->grid_max), dim3(p->NT),
-                               p->lds_bytes, s, p->args, (const uint64_t*)p->d_ops,
-                               (const int8_t*)llr, ad->d_idx, ad->d_count, u_hat, ok, pm, ad->d_next);
-            break;
-    }
+    if (wide_list(p->L)) launch_gathered<true>(ad, llr, u_hat, ok, pm, s);
+    else launch_gathered<false>(ad, llr, u_hat, ok, pm, s);
     if (n_list) hipLaunchKernelGGL(copy_count, dim3(1), dim3(1), 0, s, ad->d_count, n_list);
     return hipGetLastError() == hipSuccess ? PSCL_OK : PSCL_E_HIP;
 }

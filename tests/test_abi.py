@@ -134,7 +134,12 @@ def test_plan_create_validates_before_touching_the_device(pk):
     assert pk.lib.pscl_plan_create(8, 4, u8, 0x7, 8, 4, 0, 4, 0, ctypes.byref(h)) == 1
     # bad dtype, bad L
     assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 4, 9, 4, 0, ctypes.byref(h)) == 1
-    assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 64, 0, 4, 0, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 256, 0, 4, 0, ctypes.byref(h)) == 1
+    assert pk.lib.pscl_plan_create(8, 4, u8, 0, 0, 48, 0, 4, 0, ctypes.byref(h)) == 1
+    # L = 128 needs two wavefronts (at most 64 paths per wavefront)
+    cfg = pk.LaunchCfg(64, 0, 0)
+    assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 128, 0, 4, 0, ctypes.byref(cfg),
+                                       ctypes.byref(h)) == 2
     assert not h.value
 
 
