@@ -279,6 +279,45 @@ def fer_sweep_leg(pk, torch, code, frames_per_point, points=(3.5, 3.75, 4.0, 4.2
     return out
 
 
+def crc_length_leg(pk, torch, synth, frames_per_point, points=(2.0, 2.5, 3.0, 3.5, 4.0, 4.5, 5.0),
+                   L=128, dtype="f32", chunk=65536, seed=0x43524331):
+    """Sec. VII-B: 860 payload bits with an 8-bit or a 32-bit CRC (polar codes
+    (1024,868) and (1024,892), construction at 4.0 dB for the payload rate),
+    list size 128, frame error rate over Eb/N0 with frames made on the
+    device; plus each code's decoding throughput at L = 128."""
+    out = {}
+    for r, poly in ((8, synth.CRC8_POLY), (32, synth.CRC32_POLY)):
+        code = synth.make_code(1024, 860 + r, r, poly, 4.0)
+        gen = pk.Generator(code.N, code.K, code.frozen, code.poly, r, dtype)
+        plan = pk.Plan(code.N, code.K, code.frozen, code.poly, r, L, dtype)
+        llr, info = gen.generate(chunk, points[0], seed)
+        u, ok, pm = plan.decode(llr)
+        rows = {}
+        dec_ms = 0.0
+        for e in points:
+            errs = done = 0
+            while done < frames_per_point:
+                F = min(chunk, frames_per_point - done)
+                gen.generate(F, e, seed, first_frame=done, llr=llr[:F], info=info[:F])
+                e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e1.record()
+                plan.decode(llr[:F], u[:F], ok[:F], pm[:F])
+                e2.record()
+                errs += int((u[:F, :860] != info[:F, :860]).any(dim=1).sum().item())
+                dec_ms += e1.elapsed_time(e2)
+                done += F
+            lo, hi = wilson(errs, done)
+            rows[str(e)] = {"frames": done, "errors": errs, "fer": errs / done,
+                            "ci95": [round(lo, 8), round(hi, 8)]}
+        n_all = frames_per_point * len(points)
+        out[f"crc{r}"] = {"code": f"(1024,{860 + r})", "points": rows,
+                          "gbps": round(n_all * 860 / (dec_ms * 1e-3) / 1e9, 4),
+                          "launch": plan.info()}
+        gen.close()
+        plan.close()
+    return out
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -304,6 +343,10 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-decoding leg")
     ap.add_argument("--no-spc-plus", action="store_true", help="skip the SPC-4 vs SPC-4+ leg")
     ap.add_argument("--no-fer-sweep", action="store_true", help="skip the FER sweep leg")
+    ap.add_argument("--no-crc-study", action="store_true",
+                    help="skip the CRC-length study (1024,860) at L=128")
+    ap.add_argument("--crc-study-frames", type=int, default=1 << 19,
+                    help="frames per Eb/N0 point of the CRC-length study")
     ap.add_argument("--sweep-frames", type=int, default=1 << 20,
                     help="frames per Eb/N0 point of the FER sweep (made on the device)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -418,7 +461,11 @@ def main():
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
 
-    mixed = serving = adaptive = spc_plus = sweep = None
+    mixed = serving = adaptive = spc_plus = sweep = crc_study = None
+    if not args.single and not args.no_crc_study:
+        print(f"[bench] CRC-length study at L=128, {args.crc_study_frames} frames per point",
+              file=sys.stderr, flush=True)
+        crc_study = crc_length_leg(pk, torch, synth, args.crc_study_frames)
     if not args.single and not args.no_fer_sweep:
         print(f"[bench] FER sweep, {args.sweep_frames} device-made frames per point",
               file=sys.stderr, flush=True)
@@ -462,6 +509,7 @@ def main():
         "adaptive": adaptive,
         "spc4_vs_spc4plus": spc_plus,
         "fer_sweep": sweep,
+        "crc_length_L128": crc_study,
         "mixed": mixed,
         "serving": serving,
     }

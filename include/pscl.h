@@ -121,18 +121,18 @@ pscl_status pscl_plan_create(int N, int K, const uint8_t* frozen_mask, uint64_t 
 /*
  * Launch shape of a plan.  A zero field takes the library default for the
  * dtype (float32: 128 threads, 24 KiB; int16: 64 threads, 12 KiB; int8: 64
- * threads, 10 KiB, chosen by measurement at (2048,1723) L=32; above L = 32
- * the budget scales by L / 32 and the threads rise to at least L), which the
- * environment variables PSCL_THREADS, PSCL_LDS_BUDGET and
- * PSCL_MAX_WG_PER_CU override.
+ * threads, 10 KiB, chosen by measurement at (2048,1723) L=32; for L = 64 /
+ * 128: float32 128 / 256 threads with 32 / 48 KiB, int16 128 threads with
+ * 20 / 32 KiB, int8 128 threads with 16 / 20 KiB), which the environment
+ * variables PSCL_THREADS, PSCL_LDS_BUDGET and PSCL_MAX_WG_PER_CU override.
  *   threads: threads per workgroup (one frame per workgroup): 64, 128, 256,
  *            512 or 1024; at least 128 for L = 128 (one wavefront serves at
  *            most 64 paths), else PSCL_E_UNSUPPORTED.
  *   lds_budget: LDS bytes per workgroup (one frame) for the path tables, candidate
  *            scratch and the low tree levels' LLR stages and partial sums;
  *            the levels that do not fit go to the global workspace.  A
- *            budget too small for the tables alone is raised to the
- *            hardware limit.
+ *            budget too small for the tables alone is raised to what they
+ *            need (every tree level then in the workspace).
  */
 typedef struct {
     int threads;

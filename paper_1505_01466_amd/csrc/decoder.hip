@@ -2214,9 +2214,19 @@ static void drop_cached_groups(const pscl_plan* p) {
     for (pscl_group* g : dead) pscl_group_destroy(g);
 }
 
-static void default_launch(int dtype, int& threads, int& budget, int& wg_cap) {
+static void default_launch(int dtype, int L, int& threads, int& budget, int& wg_cap) {
     threads = dtype == PSCL_F32 ? 128 : 64;
     budget = dtype == PSCL_F32 ? 24 * 1024 : (dtype == PSCL_I16 ? 12 * 1024 : 10 * 1024);
+    if (L > 32) {
+        // measured at (2048,1723), 32,768 frames: the path tables and
+        // candidate scratch grow with L, and two wavefronts per frame pay
+        // off from 64 paths on
+        const bool big = L > 64;
+        threads = dtype == PSCL_F32 && big ? 256 : 128;
+        budget = dtype == PSCL_F32   ? (big ? 48 : 32) * 1024
+                 : dtype == PSCL_I16 ? (big ? 32 : 20) * 1024
+                                     : (big ? 20 : 16) * 1024;
+    }
     wg_cap = 0;
     if (const char* e = getenv("PSCL_THREADS")) threads = atoi(e);
     if (const char* e = getenv("PSCL_LDS_BUDGET")) budget = atoi(e);
@@ -2293,11 +2303,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (!valid_L(L) || dtype < PSCL_F32 || dtype > PSCL_I8) return PSCL_E_INVALID;
     if (mode != PSCL_MODE_TREE && mode != PSCL_MODE_SCL_LEAVES) return PSCL_E_INVALID;
     int NT = 0, budget = 0, wg_cap = 0;
-    default_launch(dtype, NT, budget, wg_cap);
-    // lists above 32: the path tables and candidate scratch grow with L, so
-    // the default budget does too; one wavefront serves at most 64 paths
-    if (L > 32 && !getenv("PSCL_LDS_BUDGET")) budget *= L / 32;
-    if (NT < L && !getenv("PSCL_THREADS")) NT = L;
+    default_launch(dtype, L, NT, budget, wg_cap);
     if (cfg && cfg->threads) NT = cfg->threads;
     if (cfg && cfg->lds_budget) budget = cfg->lds_budget;
     if (cfg && cfg->max_wg_per_cu) wg_cap = cfg->max_wg_per_cu;
@@ -2347,16 +2353,10 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
         --k_glob;
         bytes = layout(p, k_glob, lay, a);
     }
-    if (bytes + sched_need > lds_cap && lds_cap < lds_hw) {
-        // the requested budget is too small for this code: use the hardware cap
-        lds_cap = lds_hw;
-        k_glob = p->n + 1;
-        bytes = layout(p, k_glob, lay, a);
-        while (bytes + sched_need > lds_cap && k_glob > 0) {
-            --k_glob;
-            bytes = layout(p, k_glob, lay, a);
-        }
-    }
+    // a budget too small even for the path tables and candidate scratch
+    // (k_glob = 0, every tree level in the workspace) takes that smallest
+    // layout
+    if (bytes + sched_need > lds_cap) lds_cap = std::min(lds_hw, bytes + sched_need);
     if (bytes + sched_need > lds_cap) {
         delete p;
         return PSCL_E_UNSUPPORTED;
@@ -2571,8 +2571,8 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
     }
     const int dtype = plans[0]->dtype;
     int NT = 0, budget = 0, cap_unused = 0, max_L = 1;
-    default_launch(dtype, NT, budget, cap_unused);
     for (int i = 0; i < n_plans; ++i) max_L = std::max(max_L, plans[i]->L);
+    default_launch(dtype, max_L, NT, budget, cap_unused);
     if (NT < max_L && !getenv("PSCL_THREADS")) NT = max_L;  // at most 64 paths per wavefront
     if (cfg && cfg->threads) NT = cfg->threads;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;

@@ -91,14 +91,19 @@ def test_headline_code_at_L128(pk, dtype):
 
 
 @pytest.mark.parametrize("L,threads,budget", [(64, 64, 0), (64, 128, 0), (64, 256, 32768),
-                                              (128, 128, 0), (128, 256, 0), (128, 512, 65536)])
+                                              (128, 128, 0), (128, 256, 0), (128, 512, 65536),
+                                              (128, 128, 4096)])
 def test_launch_shapes(pk, L, threads, budget):
+    """Including a budget below the path tables' own size: every tree level
+    then lives in the workspace."""
     import torch
 
     code, b = batch(1024, 892, 32, synth.CRC32_POLY, 4.0, 150, 3.0, (12, L, threads), "i16")
     _say(f"(1024,892) L={L} threads={threads} budget={budget} i16")
     plan = pk.Plan(1024, 892, code.frozen, code.poly, 32, L, "i16", threads=threads,
                    lds_budget=budget)
+    if budget == 4096:
+        assert plan.info()["first_global_stage"] == 0
     g = gpu_decode(code, L, b.llr, "i16", plan=plan)
     o = oracle_decode(code, L, b.llr, "i16")
     compare(g, o, "i16", f"L={L} threads={threads}")
