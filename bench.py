@@ -318,6 +318,59 @@ def crc_length_leg(pk, torch, synth, frames_per_point, points=(2.0, 2.5, 3.0, 3.
     return out
 
 
+def graph_leg(pk, torch, synth, code, b, frames=64, calls=64, dtype="i8", reps=5):
+    """Many small decodes (calls x frames of the headline code, L = 32):
+    issued one by one, or captured once in a HIP graph and replayed.
+    Wall-clock microseconds per call including launch; outputs compared."""
+    calls = min(calls, b.F // frames)
+    if calls < 1:
+        return None
+    host = synth.quantize(b.llr_f32[:frames * calls], dtype)
+    llr = torch.from_numpy(host).cuda()
+    plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 32, dtype)
+    F = frames * calls
+    outs = [torch.empty((F, code.K), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    pm = torch.empty(F, dtype=torch.float32 if dtype == "f32" else torch.int32, device="cuda")
+
+    def issue(u):
+        for i in range(calls):
+            sl = slice(i * frames, (i + 1) * frames)
+            plan.decode(llr[sl], u[sl], ok[sl], pm[sl])
+
+    issue(outs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        issue(outs[0])
+    torch.cuda.synchronize()
+    eager_us = (time.perf_counter() - t0) / (reps * calls) * 1e6
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        issue(outs[1])
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        issue(outs[1])
+    outs[1].zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_us = (time.perf_counter() - t0) / (reps * calls) * 1e6
+    same = bool(torch.equal(outs[0], outs[1]))
+    del g
+    plan.close()
+    return {"dtype": dtype, "frames_per_call": frames, "calls": calls,
+            "eager_us_per_call": round(eager_us, 2), "graph_us_per_call": round(graph_us, 2),
+            "graph_equals_eager": same}
+
+
 def cpu_threads():
     try:
         n = len(os.sched_getaffinity(0))
@@ -343,6 +396,7 @@ def main():
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-decoding leg")
     ap.add_argument("--no-spc-plus", action="store_true", help="skip the SPC-4 vs SPC-4+ leg")
     ap.add_argument("--no-fer-sweep", action="store_true", help="skip the FER sweep leg")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--no-crc-study", action="store_true",
                     help="skip the CRC-length study (1024,860) at L=128")
     ap.add_argument("--crc-study-frames", type=int, default=1 << 19,
@@ -461,7 +515,10 @@ def main():
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
 
-    mixed = serving = adaptive = spc_plus = sweep = crc_study = None
+    mixed = serving = adaptive = spc_plus = sweep = crc_study = graph = None
+    if not args.single and not args.no_graph:
+        print("[bench] small decodes: eager vs graph replay", file=sys.stderr, flush=True)
+        graph = graph_leg(pk, torch, synth, code, b)
     if not args.single and not args.no_crc_study:
         print(f"[bench] CRC-length study at L=128, {args.crc_study_frames} frames per point",
               file=sys.stderr, flush=True)
@@ -510,6 +567,7 @@ def main():
         "spc4_vs_spc4plus": spc_plus,
         "fer_sweep": sweep,
         "crc_length_L128": crc_study,
+        "graph_replay": graph,
         "mixed": mixed,
         "serving": serving,
     }

@@ -136,3 +136,24 @@ def test_mixed_launch_with_large_lists(pk):
         _say(f"mixed ({code.N},{code.K}) L={L}")
         o = oracle_decode(code, L, b.llr, "i8")
         compare((u.cpu().numpy(), ok.cpu().numpy(), pm.cpu().numpy()), o, "i8", f"mixed L={L}")
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_largest_code_and_ragged_batches_at_L128(pk, dtype):
+    """N = 4096 at L = 128, and batches of 0, 1 and 3 frames."""
+    import torch
+
+    code, b = batch(4096, 3441, 32, synth.CRC32_POLY, 4.0, 24, 3.5, (14,), dtype)
+    _say(f"(4096,3441) L=128 {dtype}")
+    g = gpu_decode(code, 128, b.llr, dtype)
+    o = oracle_decode(code, 128, b.llr, dtype)
+    compare(g, o, dtype, "(4096,3441) L=128")
+    plan = pk.Plan(4096, 3441, code.frozen, code.poly, 32, 128, dtype)
+    for F in (0, 1, 3):
+        u, ok, pm = plan.decode(torch.from_numpy(np.ascontiguousarray(b.llr[:F])).cuda())
+        torch.cuda.synchronize()
+        assert u.shape == (F, 3441)
+        if F:
+            compare((u.cpu().numpy(), ok.cpu().numpy(), pm.cpu().numpy()),
+                    tuple(x[:F] for x in o), dtype, f"ragged F={F}")
+    plan.close()
