@@ -119,3 +119,31 @@ def test_admission_control(env):
     torch.cuda.synchronize()
     _check([out_big, out_small], _alone(torch, plans, [(2, big_llr), small]))
     sv.close()
+
+
+def test_server_with_large_lists(env):
+    """A server over plans of L = 128, 64 and 8 (its launches run the
+    wide-list kernel instance): every request equals decoding it alone."""
+    pk, torch, _, _ = env
+    specs = [(256, 128, 8, synth.CRC8_POLY, 2.5, 128, 1.5), (1024, 892, 32, synth.CRC32_POLY, 4.0, 64, 3.5),
+             (512, 256, 8, synth.CRC8_POLY, 2.5, 8, 2.0)]
+    codes, plans = [], []
+    for N, K, r, poly, d, L, _ in specs:
+        code = synth.make_code(N, K, r, poly, d)
+        codes.append(code)
+        plans.append(pk.Plan(N, K, code.frozen, poly, r, L, "i8"))
+    rng = np.random.default_rng(77)
+    work = []
+    for i in range(24):
+        pi = int(rng.integers(len(specs)))
+        b = synth.make_batch(codes[pi], int(rng.integers(1, 33)), specs[pi][6], (77, i), "i8")
+        work.append((pi, torch.from_numpy(b.llr).cuda()))
+    ref = _alone(torch, plans, work)
+    sv = pk.Server(plans, streams=2)
+    tickets = [sv.submit(pi, llr) for pi, llr in work]
+    for t, _ in tickets:
+        sv.wait(t)
+    torch.cuda.synchronize()
+    _check([o for _, o in tickets], ref)
+    _say(f"server with L up to 128: {sv.stats()}")
+    sv.close()
