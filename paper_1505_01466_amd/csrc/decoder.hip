@@ -1457,6 +1457,15 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
                 uint64_t v[1] = {lane < n ? ck[lane] : 0ull};
                 bitonic_sort<1, 64>(v);
                 if (lane < L) emit(lane, v[0]);
+            } else if (n <= 128) {
+                // two keys per lane (every Rate-1 selection fits)
+                uint64_t v[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) v[t] = lane * 2 + t < n ? ck[lane * 2 + t] : 0ull;
+                bitonic_sort<2, 64>(v);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (lane * 2 + t < L) emit(lane * 2 + t, v[t]);
             } else {
                 // at most 8 L = 256 keys, four per lane
                 uint64_t v[4];
