@@ -229,3 +229,23 @@ def test_generator_validates_arguments(pk):
     assert not h.value
     assert pk.lib.pscl_generate(None, 1, 0, 1, 4.0, None, None, None) == 1
     pk.lib.pscl_generator_destroy(None)
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """The package has no CPU fallback: a copy of it without libpscl.so
+    refuses to import."""
+    import shutil
+    import subprocess
+    import sys
+
+    src = os.path.join(ROOT, "paper_1505_01466_amd")
+    dst = tmp_path / "paper_1505_01466_amd"
+    dst.mkdir()
+    for name in os.listdir(src):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(src, name), dst / name)
+    r = subprocess.run([sys.executable, "-c", "import paper_1505_01466_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=120,
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)})
+    assert r.returncode != 0
+    assert "libpscl.so not found" in r.stderr
