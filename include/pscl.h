@@ -360,7 +360,9 @@ void pscl_generator_destroy(pscl_generator* gen);
 
 /* Frames first_frame .. first_frame + F - 1 into llr (device, F x N in the
  * dtype) and, when not NULL, their K information bits into info (device,
- * F x K bytes: payload then CRC), asynchronously on the stream. */
+ * F x K bytes: payload then CRC), asynchronously on the stream.  The device
+ * current at pscl_generator_create must be current (else PSCL_E_INVALID);
+ * F = 0 does nothing. */
 pscl_status pscl_generate(pscl_generator* gen, uint64_t seed, int64_t first_frame, int64_t F,
                           double ebn0_db, void* llr, uint8_t* info, void* stream);
 

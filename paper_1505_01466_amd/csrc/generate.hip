@@ -160,6 +160,7 @@ pscl_status hip_st(hipError_t e) {
 
 struct pscl_generator {
     int N = 0, K = 0, r = 0, dtype = 0;
+    int device = 0;  // the tables live on this device
     uint16_t* d_info = nullptr;
     uint64_t* d_crc = nullptr;
 };
@@ -198,7 +199,10 @@ pscl_status pscl_generator_create(int N, int K, const uint8_t* frozen_mask, uint
             if (carry) v ^= crc_poly & mask;
         }
     }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
     pscl_generator* g = new pscl_generator();
+    g->device = dev;
     g->N = N;
     g->K = K;
     g->r = crc_len;
@@ -222,6 +226,8 @@ pscl_status pscl_generate(pscl_generator* g, uint64_t seed, int64_t first_frame,
     if (!g || F < 0 || first_frame < 0) return PSCL_E_INVALID;
     if (F == 0) return PSCL_OK;
     if (!llr) return PSCL_E_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device) return PSCL_E_INVALID;
     const double R = (double)(g->K - g->r) / g->N;
     const double sigma2 = 1.0 / (2.0 * R * std::pow(10.0, ebn0_db / 10.0));
     const float sigma = (float)std::sqrt(sigma2), scale = (float)(2.0 / sigma2);
