@@ -8,7 +8,6 @@ positions {0, 1, 2, 4}).
 
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass, field
 
 import numpy as np

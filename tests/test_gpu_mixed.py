@@ -5,7 +5,6 @@ and match the oracle to the parity bar."""
 
 import sys
 
-import numpy as np
 import pytest
 
 import synth
