@@ -92,7 +92,8 @@ def test_headline_code_at_L128(pk, dtype):
 
 @pytest.mark.parametrize("L,threads,budget", [(64, 64, 0), (64, 128, 0), (64, 256, 32768),
                                               (128, 128, 0), (128, 256, 0), (128, 512, 65536),
-                                              (128, 128, 4096)])
+                                              (128, 128, 4096), (128, 1024, 0), (64, 1024, 0),
+                                              (32, 1024, 0)])
 def test_launch_shapes(pk, L, threads, budget):
     """Including a budget below the path tables' own size: every tree level
     then lives in the workspace."""
