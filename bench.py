@@ -517,6 +517,14 @@ def main():
                "sample": f"first {S} frames of the timed batch, decoder A (tree, L=32, {args.dtype})",
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
                "fer_vs_oracle": fer_cmp}
+        # one core, the setting of the paper's single-core figure
+        S1 = min(1024, S)
+        ts = time.perf_counter()
+        oracle.decode_tree(N, K, code.frozen, code.poly, r, L, host_llr[:S1], args.dtype, threads=1)
+        t1 = time.perf_counter() - ts
+        cpu["one_core"] = {"value": round(S1 * PAYLOAD / t1 / 1e9, 7), "unit": "Gbps",
+                           "frames": S1, "seconds": round(t1, 3),
+                           "us_per_frame": round(t1 / S1 * 1e6, 1)}
 
     mixed = serving = adaptive = spc_plus = sweep = crc_study = graph = None
     if not args.single and not args.no_graph:
