@@ -116,6 +116,29 @@ struct Dom<int16_t> : DomI<32767> {};
 template <>
 struct Dom<int8_t> : DomI<127> {};
 
+// Ranking keys of candidates, larger = better: the metric, then the smaller
+// enumeration index e.  In general the metric's order above 0xffff - e in 64
+// bits.  int8 metrics lie in [-127 N, 0] with N <= 4096, inside [-2^19, 0],
+// and e < 1024, so the same order fits 32 bits: (PM + 2^19) << 12 | 0xfff - e
+// (never 0, the padding every real key beats).
+template <typename T>
+struct Rank {
+    using K = uint64_t;
+    using M = typename Dom<T>::M;
+    static DEV K make(M v, int e) {
+        return ((uint64_t)Dom<T>::order(v) << 32) | (uint32_t)(0xffff - e);
+    }
+    static DEV M pm(K k) { return Dom<T>::from_order((uint32_t)(k >> 32)); }
+    static DEV int idx(K k) { return 0xffff - (int)(k & 0xffff); }
+};
+template <>
+struct Rank<int8_t> {
+    using K = uint32_t;
+    static DEV K make(int v, int e) { return ((uint32_t)(v + (1 << 19)) << 12) | (uint32_t)(0xfff - e); }
+    static DEV int pm(K k) { return (int)(k >> 12) - (1 << 19); }
+    static DEV int idx(K k) { return 0xfff - (int)(k & 0xfff); }
+};
+
 // ---------------------------------------------------------------------------
 // 16-byte vector access to LLR stages.
 // ---------------------------------------------------------------------------
@@ -685,6 +708,27 @@ DEV void xpair64(uint64_t v, uint64_t& a, uint64_t& b) {
 
 // The same for a distance m known only at run time (uniform across the
 // wavefront); after unrolling with a constant m the switch folds away.
+// Either key width.
+template <int M>
+DEV void xpair(uint32_t v, uint32_t& a, uint32_t& b) {
+    xpair32<M>(v, a, b);
+}
+template <int M>
+DEV void xpair(uint64_t v, uint64_t& a, uint64_t& b) {
+    xpair64<M>(v, a, b);
+}
+template <typename K>
+DEV void xpair_dyn(K v, int m, K& a, K& b) {
+    switch (m) {
+        case 1: xpair<1>(v, a, b); break;
+        case 2: xpair<2>(v, a, b); break;
+        case 4: xpair<4>(v, a, b); break;
+        case 8: xpair<8>(v, a, b); break;
+        case 16: xpair<16>(v, a, b); break;
+        default: xpair<32>(v, a, b); break;
+    }
+}
+
 DEV void xpair64_dyn(uint64_t v, int m, uint64_t& a, uint64_t& b) {
     switch (m) {
         case 1: xpair64<1>(v, a, b); break;
@@ -850,12 +894,11 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
     const int lc = ilog2u(ccount);
     const int s = q.p;
     const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, s));
-    uint64_t* ck = c.ckey() + (s << lc);
+    using RK = Rank<T>;
+    typename RK::K* ck = (typename RK::K*)c.ckey() + (s << lc);
     uint16_t* si = c.sinfo() + s * 8;
     const M pms = c.pm()[s];
-    auto put = [&](int r, M v) {
-        ck[r] = ((uint64_t)D::order(v) << 32) | (uint32_t)(0xffff - ((s << lc) + r));
-    };
+    auto put = [&](int r, M v) { ck[r] = RK::make(v, (s << lc) + r); };
     if constexpr (TYPE == OP_REP) {
         // penalties of the all-zero and all-one words (Sec. III-E)
         S z = 0, o = 0;
@@ -1010,8 +1053,8 @@ DEV constexpr uint64_t lanes_bit_clear(int b) {
 // Sorts the keys v (element i = lane * E + t of NL * E, over lanes
 // 0 .. NL - 1; NL = 32 or 64, lanes beyond NL sort their own values)
 // into descending order.
-template <int E, int NL>
-DEV void bitonic_sort(uint64_t (&v)[E]) {
+template <int E, int NL, typename K>
+DEV void bitonic_sort(K (&v)[E]) {
     // In a step (k, j) element i keeps the larger of its pair when
     // (i & k) == 0 and (i & j) == 0 agree.  Once k >= E that is the same
     // for the E elements of a lane, so each step's direction is a constant
@@ -1028,7 +1071,7 @@ DEV void bitonic_sort(uint64_t (&v)[E]) {
                 for (int t = 0; t < E; ++t) {
                     const int l = t ^ j;
                     if (l > t) {
-                        const uint64_t a = v[t], b2 = v[l];
+                        const K a = v[t], b2 = v[l];
                         bool keep;  // v[t] keeps the larger key
                         if (k < E) {
                             const bool desc = (t & k) == 0;
@@ -1047,8 +1090,8 @@ DEV void bitonic_sort(uint64_t (&v)[E]) {
                 const uint64_t want_max = ~(lanes_bit_clear(k / E) ^ lanes_bit_clear(m));
 #pragma unroll
                 for (int t = 0; t < E; ++t) {
-                    uint64_t pa, pb;
-                    xpair64_dyn(v[t], m, pa, pb);
+                    K pa, pb;
+                    xpair_dyn(v[t], m, pa, pb);
                     const bool take_a =
                         __builtin_amdgcn_inverse_ballot_w64(~(__ballot(pa > pb) ^ want_max));
                     v[t] = take_a ? pa : pb;
@@ -1058,13 +1101,13 @@ DEV void bitonic_sort(uint64_t (&v)[E]) {
     }
 }
 
-template <int E>
-DEV void bitonic_select(const uint64_t* ck, uint64_t* skey, int lane, int C, int L) {
-    uint64_t v[E];
+template <int E, typename K>
+DEV void bitonic_select(const K* ck, K* skey, int lane, int C, int L) {
+    K v[E];
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int e = lane * E + t;
-        v[t] = e < C ? ck[e] : 0ull;
+        v[t] = e < C ? ck[e] : K(0);
     }
     bitonic_sort<E, 64>(v);
 #pragma unroll
@@ -1082,35 +1125,37 @@ DEV void bitonic_select(const uint64_t* ck, uint64_t* skey, int lane, int C, int
 template <typename T, bool WIDE>
 DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
     if (c.tid >= 64) return;
+    using K = typename Rank<T>::K;
     const int lane = c.lane;
-    uint64_t* ck = c.ckey();
+    K* ck = (K*)c.ckey();
+    K* sk = (K*)c.skey();
     if (C <= 64) {
-        bitonic_select<1>(ck, c.skey(), lane, C, L);
+        bitonic_select<1>(ck, sk, lane, C, L);
         return;
     }
-    uint64_t t0 = 0ull;
+    K t0 = 0;
     if (P == L) {
-        uint64_t v;
+        K v;
         if constexpr (WIDE) {
-            v = ~0ull;
-            for (int s = lane; s < P; s += 64) v = umin64(v, ck[s << lc]);
+            v = ~K(0);
+            for (int s = lane; s < P; s += 64) v = ck[s << lc] < v ? ck[s << lc] : v;
         } else {
-            v = lane < P ? ck[lane << lc] : ~0ull;
+            v = lane < P ? ck[lane << lc] : ~K(0);
         }
         xor_steps(64, [&](auto mc) {
-            uint64_t pa, pb;
-            xpair64<decltype(mc)::value>(v, pa, pb);
-            v = umin64(pa, pb);
+            K pa, pb;
+            xpair<decltype(mc)::value>(v, pa, pb);
+            v = pa < pb ? pa : pb;
         });
         t0 = v;
     }
     // compacted in place: a chunk writes only below the end of the chunk it
     // has just read, and the wavefront's LDS accesses complete in order
-    uint64_t* kept = ck;
+    K* kept = ck;
     int n = 0;
     for (int base = 0; base < C; base += 64) {
         const int e = base + lane;
-        const uint64_t key = e < C ? ck[e] : 0ull;
+        const K key = e < C ? ck[e] : K(0);
         const bool keep = e < C && key >= t0;
         const uint64_t bal = __ballot(keep);
         const int pos = n + (int)__builtin_popcountll(bal & ((1ull << lane) - 1ull));
@@ -1131,7 +1176,7 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
             for (int base = 0; base < n; base += 256) {
                 const int cn = last ? n : (n - base < 256 ? n - base : 256);
                 const int keep = last ? L : (cn < L ? cn : L);
-                uint64_t* dst = last ? c.skey() : kept + m;
+                K* dst = last ? sk : kept + m;
                 if (cn <= 64) bitonic_select<1>(kept + base, dst, lane, cn, keep);
                 else if (cn <= 128) bitonic_select<2>(kept + base, dst, lane, cn, keep);
                 else bitonic_select<4>(kept + base, dst, lane, cn, keep);
@@ -1143,9 +1188,9 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
             n = m;
         }
     } else {
-        if (n <= 64) bitonic_select<1>(kept, c.skey(), lane, n, L);
-        else if (n <= 128) bitonic_select<2>(kept, c.skey(), lane, n, L);
-        else bitonic_select<4>(kept, c.skey(), lane, n, L);
+        if (n <= 64) bitonic_select<1>(kept, sk, lane, n, L);
+        else if (n <= 128) bitonic_select<2>(kept, sk, lane, n, L);
+        else bitonic_select<4>(kept, sk, lane, n, L);
     }
 }
 
@@ -1161,8 +1206,10 @@ DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, b
     const int j = q.p;
     // the candidate taking slot j and its key (nothing dropped: candidate j,
     // whose key is intact)
-    const uint64_t kj = prune ? c.skey()[j] : c.ckey()[j];
-    const int e = prune ? 0xffff - (int)(kj & 0xffff) : j;
+    using RK = Rank<T>;
+    const typename RK::K kj = prune ? ((const typename RK::K*)c.skey())[j]
+                                    : ((const typename RK::K*)c.ckey())[j];
+    const int e = prune ? RK::idx(kj) : j;
     const int s = e >> lc;
     const int r = e & (ccount - 1);
     const uint16_t* si = c.sinfo() + s * 8;
@@ -1194,7 +1241,7 @@ DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, b
         if (side == 0) c.rowB(nxt, j)[k] = (uint8_t)j;
         // a survivor's metric: from the selection, or (nothing dropped)
         // from its intact ranking key
-        c.pm()[j] = Dom<T>::from_order((uint32_t)(kj >> 32));
+        c.pm()[j] = RK::pm(kj);
     }
 }
 
