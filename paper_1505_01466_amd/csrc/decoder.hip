@@ -131,6 +131,31 @@ struct Rank {
     static DEV M pm(K k) { return Dom<T>::from_order((uint32_t)(k >> 32)); }
     static DEV int idx(K k) { return 0xffff - (int)(k & 0xffff); }
 };
+// Keys of positions in a node for finding the least reliable ones: |value|,
+// then the index (smaller = less reliable, ties to the lower index).  Integer
+// magnitudes (at most 32767) and indices (below 4096) fit 32 bits in the
+// same order.
+template <typename T>
+struct Lrb {
+    using K = uint64_t;
+    static DEV K make(typename Dom<T>::A v, int i) {
+        return ((uint64_t)Dom<T>::mag_key(v) << 32) | (uint32_t)i;
+    }
+    static DEV typename Dom<T>::S mag(K k) { return Dom<T>::mag_from_key((uint32_t)(k >> 32)); }
+    static DEV int idx(K k) { return (int)(k & 0xffff); }
+};
+template <typename T>
+struct LrbI {
+    using K = uint32_t;
+    static DEV K make(int v, int i) { return ((uint32_t)abs(v) << 12) | (uint32_t)i; }
+    static DEV int mag(K k) { return (int)(k >> 12); }
+    static DEV int idx(K k) { return (int)(k & 0xfff); }
+};
+template <>
+struct Lrb<int16_t> : LrbI<int16_t> {};
+template <>
+struct Lrb<int8_t> : LrbI<int8_t> {};
+
 template <>
 struct Rank<int8_t> {
     using K = uint32_t;
@@ -774,22 +799,33 @@ DEV double group_sum(double v, int G) {
 
 // The 4 smallest of two ascending 4-lists, ascending (bitonic split of a
 // against reversed b, then a 4-element bitonic merge).
-DEV void merge4(uint64_t* a, const uint64_t* b) {
-    const uint64_t l0 = umin64(a[0], b[3]), l1 = umin64(a[1], b[2]);
-    const uint64_t l2 = umin64(a[2], b[1]), l3 = umin64(a[3], b[0]);
-    const uint64_t x0 = umin64(l0, l2), x2 = umax64(l0, l2);
-    const uint64_t x1 = umin64(l1, l3), x3 = umax64(l1, l3);
-    a[0] = umin64(x0, x1);
-    a[1] = umax64(x0, x1);
-    a[2] = umin64(x2, x3);
-    a[3] = umax64(x2, x3);
+template <typename K>
+DEV K kmin(K a, K b) {
+    return a < b ? a : b;
+}
+template <typename K>
+DEV K kmax(K a, K b) {
+    return a < b ? b : a;
 }
 
-DEV void insert4(uint64_t* kk, uint64_t key) {
+template <typename K>
+DEV void merge4(K* a, const K* b) {
+    const K l0 = kmin(a[0], b[3]), l1 = kmin(a[1], b[2]);
+    const K l2 = kmin(a[2], b[1]), l3 = kmin(a[3], b[0]);
+    const K x0 = kmin(l0, l2), x2 = kmax(l0, l2);
+    const K x1 = kmin(l1, l3), x3 = kmax(l1, l3);
+    a[0] = kmin(x0, x1);
+    a[1] = kmax(x0, x1);
+    a[2] = kmin(x2, x3);
+    a[3] = kmax(x2, x3);
+}
+
+template <typename K>
+DEV void insert4(K* kk, K key) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const uint64_t lo = umin64(kk[q], key);
-        key = umax64(kk[q], key);
+        const K lo = kmin(kk[q], key);
+        key = kmax(kk[q], key);
         kk[q] = lo;
     }
 }
@@ -927,48 +963,50 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
             }
         } else {
             // two least reliable positions, ties to the lower index
-            uint64_t k1 = ~0ull, k2 = ~0ull;
+            using LK = typename Lrb<T>::K;
+            LK k1 = ~LK(0), k2 = ~LK(0);
             if (q.valid) {
                 leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
-                    const uint64_t key = ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i;
-                    const uint64_t lo = umin64(k1, key);
-                    k2 = umin64(umax64(k1, key), k2);
+                    const LK key = Lrb<T>::make(v, i);
+                    const LK lo = kmin(k1, key);
+                    k2 = kmin(kmax(k1, key), k2);
                     k1 = lo;
                 });
             }
             xor_steps(q.G, [&](auto mc) {
                 constexpr int M = decltype(mc)::value;
-                uint64_t a1, b1, a2, b2;
-                xpair64<M>(k1, a1, b1);
-                xpair64<M>(k2, a2, b2);
-                k1 = umin64(a1, b1);
-                k2 = umin64(umax64(a1, b1), umin64(a2, b2));
+                LK a1, b1, a2, b2;
+                xpair<M>(k1, a1, b1);
+                xpair<M>(k2, a2, b2);
+                k1 = kmin(a1, b1);
+                k2 = kmin(kmax(a1, b1), kmin(a2, b2));
             });
             if (q.valid && q.g == 0) {
-                const S a1 = D::mag_from_key((uint32_t)(k1 >> 32));
-                const S a2 = D::mag_from_key((uint32_t)(k2 >> 32));
+                const S a1 = Lrb<T>::mag(k1);
+                const S a2 = Lrb<T>::mag(k2);
                 put(0, pms);
                 put(1, D::sub(pms, D::round_pen(a1)));
                 put(2, D::sub(pms, D::round_pen(a2)));
                 put(3, D::sub(pms, D::round_pen(a1 + a2)));
-                si[0] = (uint16_t)(k1 & 0xffff);
-                si[1] = (uint16_t)(k2 & 0xffff);
+                si[0] = (uint16_t)Lrb<T>::idx(k1);
+                si[1] = (uint16_t)Lrb<T>::idx(k2);
             }
         }
     } else {  // OP_SPC
-        uint64_t kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+        using LK = typename Lrb<T>::K;
+        LK kk[4] = {~LK(0), ~LK(0), ~LK(0), ~LK(0)};
         int par = 0;
         if (q.valid) {
             leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
                 par ^= (v < 0) ? 1 : 0;
-                insert4(kk, ((uint64_t)D::mag_key(v) << 32) | (uint32_t)i);
+                insert4(kk, Lrb<T>::make(v, i));
             });
         }
         xor_steps(q.G, [&](auto mc) {
             constexpr int M = decltype(mc)::value;
-            uint64_t ob[4];
+            LK ob[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) xpair64<M>(kk[t], kk[t], ob[t]);
+            for (int t = 0; t < 4; ++t) xpair<M>(kk[t], kk[t], ob[t]);
             uint32_t pa, pb;
             xpair32<M>((uint32_t)par, pa, pb);
             par = (int)(pa ^ pb);
@@ -981,8 +1019,8 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
             S mag[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                idx[t] = (uint32_t)(kk[t] & 0xffff);
-                mag[t] = D::mag_from_key((uint32_t)(kk[t] >> 32));
+                idx[t] = (uint32_t)Lrb<T>::idx(kk[t]);
+                mag[t] = Lrb<T>::mag(kk[t]);
                 rk[t] = (uint32_t)t;
                 si[t] = (uint16_t)idx[t];
             }
