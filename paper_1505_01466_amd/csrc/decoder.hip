@@ -965,8 +965,10 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
             // two least reliable positions, ties to the lower index
             using LK = typename Lrb<T>::K;
             LK k1 = ~LK(0), k2 = ~LK(0);
+            uint32_t hd = 0u;  // hard decisions of a node of at most 32 values
             if (q.valid) {
                 leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
+                    if (nv <= 32) hd |= (v < 0 ? 1u : 0u) << i;
                     const LK key = Lrb<T>::make(v, i);
                     const LK lo = kmin(k1, key);
                     k2 = kmin(kmax(k1, key), k2);
@@ -980,6 +982,9 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                 xpair<M>(k2, a2, b2);
                 k1 = kmin(a1, b1);
                 k2 = kmin(kmax(a1, b1), kmin(a2, b2));
+                uint32_t ha, hb;
+                xpair32<M>(hd, ha, hb);
+                hd = ha | hb;
             });
             if (q.valid && q.g == 0) {
                 const S a1 = Lrb<T>::mag(k1);
@@ -990,15 +995,19 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                 put(3, D::sub(pms, D::round_pen(a1 + a2)));
                 si[0] = (uint16_t)Lrb<T>::idx(k1);
                 si[1] = (uint16_t)Lrb<T>::idx(k2);
+                si[6] = (uint16_t)hd;
+                si[7] = (uint16_t)(hd >> 16);
             }
         }
     } else {  // OP_SPC
         using LK = typename Lrb<T>::K;
         LK kk[4] = {~LK(0), ~LK(0), ~LK(0), ~LK(0)};
         int par = 0;
+        uint32_t hd = 0u;  // hard decisions of a node of at most 32 values
         if (q.valid) {
             leaf_scan<T, ISP>(in, nv, q.g, q.G, [&](int i, A v) {
                 par ^= (v < 0) ? 1 : 0;
+                if (nv <= 32) hd |= (v < 0 ? 1u : 0u) << i;
                 insert4(kk, Lrb<T>::make(v, i));
             });
         }
@@ -1010,6 +1019,8 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
             uint32_t pa, pb;
             xpair32<M>((uint32_t)par, pa, pb);
             par = (int)(pa ^ pb);
+            xpair32<M>(hd, pa, pb);
+            hd = pa | pb;
             merge4(kk, ob);
         });
         if (q.valid && q.g == 0) {
@@ -1041,6 +1052,8 @@ DEV void pp_fork_score(const Ctx<T>& c, const OpRec& op, int k, int ccount, cons
                 }
             }
             si[4] = (uint16_t)par;
+            si[6] = (uint16_t)hd;
+            si[7] = (uint16_t)(hd >> 16);
             const uint32_t base_d = par ? 1u : 0u;  // ML flips m1 when parity fails
             for (int r = 0; r < ccount; ++r) {
                 const uint32_t dm = spc_flips(r) ^ base_d;
@@ -1260,7 +1273,9 @@ DEV void pp_fork_emit(Ctx<T>& c, const OpRec& op, int k, int side, int ccount, b
         if (TYPE == OP_REP || (TYPE == OP_R1 && k == 0)) {
             word = ((si[4] ^ r) & 1) ? full : 0u;
         } else {
-            word = hd_word<T>(in, w, nv);
+            // hard decisions: kept by the scoring pass for nodes of at most
+            // 32 values, else recomputed from the source's input
+            word = nv <= 32 ? ((uint32_t)si[6] | ((uint32_t)si[7] << 16)) : hd_word<T>(in, w, nv);
             uint32_t dm;
             if constexpr (TYPE == OP_R1) dm = (uint32_t)r;
             else dm = spc_flips(r) ^ (si[4] ? 1u : 0u);
