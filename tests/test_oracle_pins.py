@@ -450,3 +450,25 @@ def test_near_tie_flag(orc):
     a = np.array([3, -3], np.int8)
     _, _, _, nt = orc.decode_tree(2, 2, frozen, 0, 0, 2, a, "i8")
     assert nt[0] == 0
+
+
+def test_int8_metrics_stay_within_127_N():
+    """Every int8 path metric lies in [-127 N, 0]: a position's |LLR| is at
+    most 127 after saturation and each position is charged by one leaf only.
+    (The int8 kernels pack metric and candidate index into 32-bit ranking
+    keys on this bound.)  Checked on the whole final list, with saturated and
+    adversarial inputs, including every-value-negative frames."""
+    import oracle
+
+    rng = np.random.default_rng(127)
+    for N, K, L in ((4096, 3441, 32), (1024, 512, 128), (256, 128, 32)):
+        code = synth.make_code(N, K, 0, 0, 2.0)
+        for trial in range(3):
+            if trial == 0:
+                llr = np.where(rng.random(N) < 0.5, -127, 127).astype(np.int8)
+            elif trial == 1:
+                llr = np.full(N, -127, np.int8)
+            else:
+                llr = rng.integers(-128, 128, N).astype(np.int8)
+            _, pm = oracle.decode_tree_list(N, K, code.frozen, L, llr[None, :], "i8")
+            assert pm.max() <= 0 and pm.min() >= -127 * N, (N, trial, pm.min())
