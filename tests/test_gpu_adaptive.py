@@ -41,7 +41,7 @@ def _oracle_adaptive(code, L, llr, dtype):
     return (u, ok, pm, nt), fail.size
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f32"])
+@pytest.mark.parametrize("dtype", ["i8", "i16", "f32"])
 @pytest.mark.parametrize("case", [(256, 128, 8, synth.CRC8_POLY, 2.0, 8, 400, 1.5),
                                   (2048, 1723, 32, synth.CRC32_POLY, 4.0, 32, 300, 3.5),
                                   (1024, 512, 8, synth.CRC8_POLY, 2.5, 4, 257, 2.0),

@@ -33,7 +33,9 @@ CODES = [(2048, 1723, 32, synth.CRC32_POLY, 4.0, 300, 4.0),
          (1024, 512, 8, synth.CRC8_POLY, 2.5, 257, 2.0),
          (256, 128, 0, 0, 2.0, 129, 1.0),
          (64, 40, 8, synth.CRC8_POLY, 3.0, 65, 6.0),
-         (4096, 3441, 32, synth.CRC32_POLY, 4.0, 33, 3.0)]
+         (4096, 3441, 32, synth.CRC32_POLY, 4.0, 33, 3.0),
+         (16, 8, 4, 0x3, 2.0, 50, 4.0),
+         (2, 1, 0, 0, 2.0, 20, 3.0)]
 
 
 def _check_llr(dev, host, dtype, scale):
