@@ -57,7 +57,7 @@ def _same(a, b):
     return all(bool((x == y).all()) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("dtype", ["i8", "f32"])
+@pytest.mark.parametrize("dtype", ["i8", "i16", "f32"])
 def test_group_equals_single_plan_decodes(env, dtype):
     pk, torch = env
     frames = [(0, 37), (3, 5), (1, 100), (2, 0), (4, 3), (2, 64), (0, 1), (3, 9)]
