@@ -147,3 +147,31 @@ def test_server_with_large_lists(env):
     _check([o for _, o in tickets], ref)
     _say(f"server with L up to 128: {sv.stats()}")
     sv.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "i16"])
+def test_server_other_dtypes(env, dtype):
+    """The server over float32 or int16 plans: every request equals decoding
+    it alone (float32 bit for bit as well: the same kernel code per frame)."""
+    pk, torch, _, _ = env
+    specs = CODES[:3]
+    codes, plans = [], []
+    for N, K, r, poly, d, L in specs:
+        code = synth.make_code(N, K, r, poly, d)
+        codes.append(code)
+        plans.append(pk.Plan(N, K, code.frozen, code.poly, r, L, dtype))
+    rng = np.random.default_rng(91)
+    work = []
+    for i in range(20):
+        pi = int(rng.integers(len(specs)))
+        b = synth.make_batch(codes[pi], int(rng.integers(1, 40)), specs[pi][4], (91, i), dtype)
+        work.append((pi, torch.from_numpy(b.llr).cuda()))
+    ref = _alone(torch, plans, work)
+    sv = pk.Server(plans, streams=2)
+    tickets = [sv.submit(pi, llr) for pi, llr in work]
+    for t, _ in tickets:
+        sv.wait(t)
+    torch.cuda.synchronize()
+    _check([o for _, o in tickets], ref)
+    _say(f"server {dtype}: {sv.stats()}")
+    sv.close()
