@@ -174,7 +174,8 @@ void pscl_plan_destroy(pscl_plan* plan);
  *       PSCL_F32, int32 for the integer dtypes.
  *   stream: hipStream_t or NULL for the default stream.
  * F = 0 is a no-op.  Returns PSCL_E_INVALID on null required pointers or
- * F < 0.
+ * F < 0.  Only kernel launches are issued (no allocation, copy or memset),
+ * so a call can be captured in a HIP graph and replayed.
  */
 pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8_t* u_hat,
                         uint8_t* crc_ok, void* pm, void* stream);
