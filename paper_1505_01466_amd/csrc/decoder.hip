@@ -1152,7 +1152,7 @@ DEV void bitonic_sort(K (&v)[E]) {
     }
 }
 
-template <int E, typename K>
+template <int E, typename K, int NL = 64>
 DEV void bitonic_select(const K* ck, K* skey, int lane, int C, int L) {
     K v[E];
 #pragma unroll
@@ -1160,7 +1160,7 @@ DEV void bitonic_select(const K* ck, K* skey, int lane, int C, int L) {
         const int e = lane * E + t;
         v[t] = e < C ? ck[e] : K(0);
     }
-    bitonic_sort<E, 64>(v);
+    bitonic_sort<E, NL>(v);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int pos = lane * E + t;
@@ -1239,7 +1239,8 @@ DEV void select_rank(const Ctx<T>& c, int C, int L, int P, int lc) {
             n = m;
         }
     } else {
-        if (n <= 64) bitonic_select<1>(kept, sk, lane, n, L);
+        if (n <= 32) bitonic_select<1, K, 32>(kept, sk, lane, n, L);
+        else if (n <= 64) bitonic_select<1>(kept, sk, lane, n, L);
         else if (n <= 128) bitonic_select<2>(kept, sk, lane, n, L);
         else bitonic_select<4>(kept, sk, lane, n, L);
     }
@@ -1553,7 +1554,12 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
                 n += (int)__builtin_popcountll(bal);
             }
             wave_sync();
-            if (n <= 64) {
+            if (n <= 32) {
+                // exactly L = 32 kept: a 32-key network
+                uint64_t v[1] = {lane < n ? ck[lane] : 0ull};
+                bitonic_sort<1, 32>(v);
+                if (lane < L) emit(lane, v[0]);
+            } else if (n <= 64) {
                 uint64_t v[1] = {lane < n ? ck[lane] : 0ull};
                 bitonic_sort<1, 64>(v);
                 if (lane < L) emit(lane, v[0]);
