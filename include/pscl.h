@@ -28,11 +28,17 @@
  *
  * Ownership: the caller owns every device buffer passed in; a plan owns its
  * device schedule, tables and workspace.  Decoding is asynchronous on the
- * caller's HIP stream and never allocates.  A plan's workspace serves one
- * call at a time: calls on one plan must be ordered (one stream, or
- * synchronised); a group (below) keeps a workspace per call in flight, so
- * its calls may overlap on different streams.  All device pointers must be
- * accessible from the device that was current when the plan was created.
+ * caller's HIP stream.  A plan's workspace is allocated by the first
+ * pscl_decode on it (or by pscl_plan_reserve); later calls never allocate.
+ * A plan's workspace serves one call at a time: calls on one plan must be
+ * ordered (one stream, or synchronised); a group (below) keeps a workspace
+ * per call in flight, so its calls may overlap on different streams, and so
+ * may calls of the one-call form.  All device pointers must be accessible
+ * from the device that was current when the plan was created.
+ *
+ * Integer inputs: the int8 / int16 domains are [-127, 127] / [-32767,
+ * 32767]; an input of -128 / -32768 is read as -127 / -32767 (saturated on
+ * load, as every G result is).
  *
  * Errors: every function returns a status code and never throws.  A HIP
  * failure reported by the runtime (including asynchronous faults of earlier
@@ -109,7 +115,8 @@ pscl_status pscl_schedule(int N, const uint8_t* frozen_mask, int L, int spc_max,
  *   L: list size in {1, 2, 4, 8, 16, 32, 64, 128} (Sec. VII-B uses 128 for
  *   the CRC-length comparison).  dtype: pscl_dtype.
  *   spc_max, mode: see pscl_schedule.
- * Allocates the device schedule, CRC tables and decoding workspace.
+ * Allocates the device schedule and CRC tables; the decoding workspace
+ * follows on first use (pscl_plan_reserve).
  * Returns PSCL_E_INVALID on bad arguments, PSCL_E_NODEV without a gfx950
  * device, PSCL_E_NOMEM / PSCL_E_HIP on runtime failures.  *out is set only on
  * success.
@@ -163,6 +170,13 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
 /* Release a plan (NULL allowed).  Synchronises the device first. */
 void pscl_plan_destroy(pscl_plan* plan);
 
+/* Allocate the plan's decoding workspace now (pscl_decode otherwise does
+ * on its first call), so that every pscl_decode on it is free of
+ * allocation, e.g. before capturing one in a HIP graph.  Plans used only
+ * through groups or servers never need it.  Returns
+ * PSCL_E_NOMEM when the device is out of memory. */
+pscl_status pscl_plan_reserve(const pscl_plan* plan);
+
 /*
  * Decode F frames (Sec. III; Alg. 1; final CRC choice, Sec. II-B).
  *   llr: device, F x N row-major in the plan's dtype.
@@ -174,8 +188,9 @@ void pscl_plan_destroy(pscl_plan* plan);
  *       PSCL_F32, int32 for the integer dtypes.
  *   stream: hipStream_t or NULL for the default stream.
  * F = 0 is a no-op.  Returns PSCL_E_INVALID on null required pointers or
- * F < 0.  Only kernel launches are issued (no allocation, copy or memset),
- * so a call can be captured in a HIP graph and replayed.
+ * F < 0.  Once the plan's workspace exists (pscl_plan_reserve, or any
+ * earlier call) only kernel launches are issued (no allocation, copy or
+ * memset), so a call can be captured in a HIP graph and replayed.
  */
 pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8_t* u_hat,
                         uint8_t* crc_ok, void* pm, void* stream);
@@ -183,8 +198,11 @@ pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8
 /*
  * One-call form decode(N, K, frozen_mask, crc_poly, L, llr) -> u_hat: builds
  * (or reuses from a per-process cache keyed by every argument that shapes the
- * plan) the plan for the Dec-SPC-4 tree and decodes.  Same buffers and
- * errors as pscl_plan_create + pscl_decode.
+ * plan) the plan for the Dec-SPC-4 tree, with a group of it holding two
+ * workspaces, and decodes.  Calls may overlap on any threads and streams,
+ * also for one code: each call in flight has its own workspace and frame
+ * counter (a third overlapping call waits on the host for the oldest).
+ * Same buffers and errors as pscl_plan_create + pscl_group_decode.
  */
 pscl_status pscl_decode_oneshot(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
                                 int crc_len, int L, int dtype, const void* llr, int64_t F,

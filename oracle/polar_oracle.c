@@ -169,10 +169,16 @@ static double cw_penalty(const domain* d, const double* a, const uint8_t* cw, in
     return dom_round(d, s);
 }
 
+/* A channel value.  An integer domain holds [-Q, Q] (the range G saturates
+ * to), so the one input value below it (-128 for int8, -32768 for int16) is
+ * saturated to -Q on input like any G result. */
 static double llr_at(int dtype, const void* llr, int64_t idx) {
     if (dtype == ORC_F32) return (double)((const float*)llr)[idx];
-    if (dtype == ORC_I16) return (double)((const int16_t*)llr)[idx];
-    return (double)((const int8_t*)llr)[idx];
+    double v;
+    if (dtype == ORC_I16) v = (double)((const int16_t*)llr)[idx];
+    else v = (double)((const int8_t*)llr)[idx];
+    domain d = make_domain(dtype);
+    return dom_llr(&d, v);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -408,7 +414,7 @@ static void info_positions(int N, const uint8_t* frozen, int* pos) {
         if (!frozen[i]) pos[k++] = i;
 }
 
-/* Final choice (Sec. II-B, P:294): the most reliable path that satisfies the
+/* Final choice (Sec. II-B): the most reliable path that satisfies the
  * CRC; when none does (or there is no CRC) the most reliable path.  Equal
  * metrics go to the lower slot.  u is recovered from the root codeword by the
  * polar transform (an involution).  Returns the chosen slot. */

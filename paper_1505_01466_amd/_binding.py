@@ -83,6 +83,8 @@ def _load():
     lib.pscl_plan_create.restype = c_int
     lib.pscl_plan_destroy.argtypes = [vp]
     lib.pscl_plan_destroy.restype = None
+    lib.pscl_plan_reserve.argtypes = [vp]
+    lib.pscl_plan_reserve.restype = c_int
     lib.pscl_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp]
     lib.pscl_decode.restype = c_int
     lib.pscl_decode_oneshot.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, vp, c_i64,
@@ -205,6 +207,10 @@ class Plan:
         return {"frames_per_wg": fw.value, "threads": nt.value, "workgroups": wg.value,
                 "lds_bytes": lds.value, "workspace_bytes": ws.value,
                 "first_global_stage": glob.value}
+
+    def reserve(self):
+        """Allocate the plan's workspace now (pscl_plan_reserve)."""
+        _check(lib.pscl_plan_reserve(self._h), "pscl_plan_reserve")
 
     def decode(self, llr, u_hat=None, crc_ok=None, pm=None):
         """Decode llr (F x N device tensor in the plan's dtype) into

@@ -32,14 +32,37 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source into LIB_PATH (always recompiles)."""
+    """Compile every source into LIB_PATH (always recompiles): one object per
+    source, in parallel, then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB_PATH + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB_PATH)
+    tag = f".tmp{os.getpid()}"
+    objs = [os.path.join(LIB_DIR, os.path.basename(src) + tag + ".o") for src in SOURCES]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+
+    def one(args):
+        src, obj = args
+        cmd = [HIPCC, *compile_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd).returncode
+
+    try:
+        with ThreadPoolExecutor(len(SOURCES)) as ex:
+            rcs = list(ex.map(one, zip(SOURCES, objs)))
+        if any(rcs):
+            raise subprocess.CalledProcessError(max(rcs), "hipcc")
+        tmp = LIB_PATH + tag
+        cmd = [HIPCC, *FLAGS, *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB_PATH)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB_PATH
 
 

@@ -2019,9 +2019,13 @@ struct pscl_plan {
     OpRec* d_ops = nullptr;
     uint64_t* d_syn = nullptr;
     uint16_t* d_info = nullptr;
-    uint8_t* d_ws = nullptr;
+    // workspace: allocated by the first call that needs it (or by
+    // pscl_plan_reserve), so that plans used only inside groups and
+    // servers never hold one
+    mutable uint8_t* d_ws = nullptr;
+    mutable std::mutex ws_mu;
     unsigned long long* d_counter = nullptr;  // frames handed out
-    KArgs args{};
+    mutable KArgs args{};
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int64_t ws_bytes = 0;
     const void* kernel = nullptr;
@@ -2348,6 +2352,23 @@ static void default_launch(int dtype, int L, int& threads, int& budget, int& wg_
     if (const char* e = getenv("PSCL_MAX_WG_PER_CU")) wg_cap = atoi(e);
 }
 
+// The plan's own workspace (full grid), allocated on first use.
+static pscl_status ensure_workspace(const pscl_plan* p) {
+    if (p->ws_bytes <= 0) return PSCL_OK;
+    std::lock_guard<std::mutex> lk(p->ws_mu);
+    if (p->d_ws) return PSCL_OK;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return PSCL_E_HIP;
+    if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return PSCL_E_HIP;
+    uint8_t* ws = nullptr;
+    const pscl_status st = hip_status(hipMalloc((void**)&ws, (size_t)p->ws_bytes));
+    if (cur != p->device) (void)hipSetDevice(cur);
+    if (st != PSCL_OK) return st;
+    p->d_ws = ws;
+    p->args.ws = ws;
+    return PSCL_OK;
+}
+
 extern "C" {
 
 const char* pscl_status_str(pscl_status s) {
@@ -2511,7 +2532,6 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     up((void**)&p->d_ops, ops.data(), ops.size() * sizeof(OpRec));
     up((void**)&p->d_syn, syn.data(), syn.size() * 8);
     up((void**)&p->d_info, info.data(), info.size() * 2);
-    if (st == PSCL_OK && p->ws_bytes > 0) st = hip_status(hipMalloc((void**)&p->d_ws, p->ws_bytes));
     if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&p->d_counter, 8));
     if (st != PSCL_OK) {
         pscl_plan_destroy(p);
@@ -2521,7 +2541,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     a.ops = p->d_ops;
     a.syn = p->d_syn;
     a.info_pos = p->d_info;
-    a.ws = p->d_ws;
+    a.ws = nullptr;  // set when the workspace is allocated
     a.ws_frame = wsf;
     a.n_ops = (int)ops.size();
     a.N = N;
@@ -2547,6 +2567,11 @@ pscl_status pscl_plan_info(const pscl_plan* p, int* frames_per_wg, int* threads,
     return PSCL_OK;
 }
 
+pscl_status pscl_plan_reserve(const pscl_plan* p) {
+    if (!p) return PSCL_E_INVALID;
+    return ensure_workspace(p);
+}
+
 pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t* u_hat,
                         uint8_t* crc_ok, void* pm, void* stream) {
     if (!p || F < 0) return PSCL_E_INVALID;
@@ -2555,6 +2580,10 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     if (((uintptr_t)llr & 15u) != 0) return PSCL_E_INVALID;  // 16-byte vector loads
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return PSCL_E_HIP;
+    if (!p->d_ws) {
+        const pscl_status st = ensure_workspace(p);
+        if (st != PSCL_OK) return st;
+    }
     const int grid = (int)std::min<int64_t>(F, p->grid_max);
     hipStream_t s = (hipStream_t)stream;
     // the frame counter starts at zero (a one-thread kernel, so that the
@@ -2569,29 +2598,42 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
 pscl_status pscl_decode_oneshot(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
                                 int crc_len, int L, int dtype, const void* llr, int64_t F,
                                 uint8_t* u_hat, uint8_t* crc_ok, void* stream) {
-    if (!frozen_mask || N < 2 || N > 4096) return PSCL_E_INVALID;
+    if (!frozen_mask || N < 2 || N > 4096 || F < 0) return PSCL_E_INVALID;
+    if (F == 0) return PSCL_OK;
+    // The caller never sees the plan, so calls for one code may come from
+    // several threads and streams at once: each code gets a cached group
+    // whose calls in flight have their own workspace and frame counter.
     static std::mutex mu;
-    static std::map<std::string, pscl_plan*> cache;
+    static std::map<std::string, std::pair<pscl_plan*, pscl_group*>> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
     std::string key((const char*)frozen_mask, (size_t)N);
     key += std::to_string(N) + "/" + std::to_string(K) + "/" + std::to_string(crc_poly) + "/" +
            std::to_string(crc_len) + "/" + std::to_string(L) + "/" + std::to_string(dtype) + "/" +
            std::to_string(dev);
-    pscl_plan* p = nullptr;
+    pscl_group* g = nullptr;
     {
-        std::lock_guard<std::mutex> g(mu);
+        std::lock_guard<std::mutex> lk(mu);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            p = it->second;
+            g = it->second.second;
         } else {
+            pscl_plan* p = nullptr;
             pscl_status st = pscl_plan_create(N, K, frozen_mask, crc_poly, crc_len, L, dtype, 4,
                                               PSCL_MODE_TREE, &p);
             if (st != PSCL_OK) return st;
-            cache[key] = p;
+            const pscl_plan* pp = p;
+            pscl_launch_cfg cfg{p->NT, 0, 0};
+            st = pscl_group_create(&pp, 1, 1, 2, &cfg, &g);
+            if (st != PSCL_OK) {
+                pscl_plan_destroy(p);
+                return st;
+            }
+            cache[key] = {p, g};
         }
     }
-    return pscl_decode(p, llr, F, u_hat, crc_ok, nullptr, stream);
+    pscl_job job{0, llr, F, u_hat, crc_ok, nullptr};
+    return pscl_group_decode(g, &job, 1, stream);
 }
 
 pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
@@ -2866,6 +2908,8 @@ pscl_status pscl_adaptive_create(const pscl_plan* fast, const pscl_plan* list, i
                                           : gathered_kernel_for<false>(list->dtype);
     pscl_status st = hip_status(
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, list->lds_bytes));
+    if (st == PSCL_OK) st = ensure_workspace(fast);
+    if (st == PSCL_OK) st = ensure_workspace(list);
     if (st != PSCL_OK) return st;
     pscl_adaptive* ad = new pscl_adaptive();
     ad->fast = fast;

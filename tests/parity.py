@@ -30,11 +30,15 @@ def oracle_decode(code, L, llr_np, dtype, spc_max=4, mode=0):
                               spc_max=spc_max, mode=mode)
 
 
-def compare(gpu, ref, dtype, what=""):
+def compare(gpu, ref, dtype, what="", max_excused=None):
     """Integer dtypes: identical bits, CRC flags and metrics on every frame.
-    float32: identical decisions and CRC flags, metrics within REL_TOL, on
-    every frame the oracle did not flag as a metric near-tie.  Returns the
-    number of frames that are bit-identical in every output."""
+    float32: identical decisions and CRC flags with metrics within REL_TOL
+    relative on every frame, except frames the oracle flagged as metric
+    near-ties; such a frame may differ (it is "excused") only if the GPU's
+    chosen metric is still within REL_TOL of the oracle's, and at most
+    max_excused frames (default: 1% of the batch, at least one) may be
+    excused.  The excused count is printed.  Returns the number of frames
+    that are bit-identical in every output."""
     u_g, ok_g, pm_g = gpu
     u_o, ok_o, pm_o, nt = ref
     F = u_o.shape[0]
@@ -43,12 +47,20 @@ def compare(gpu, ref, dtype, what=""):
     same_ok = ok_g == ok_o
     if dtype == "f32":
         pm_g = pm_g.astype(np.float64)
-        close = np.abs(pm_g - pm_o) <= REL_TOL * np.abs(pm_o) + 1e-6
+        close = np.abs(pm_g - pm_o) <= REL_TOL * np.abs(pm_o)
         good = same_u & same_ok & close
         bad = np.flatnonzero(~good & (nt == 0))
         assert bad.size == 0, (
             f"{what}: {bad.size}/{F} frames differ without a near-tie, first {bad[:8]}; "
             f"pm gpu {pm_g[bad[:4]]} oracle {pm_o[bad[:4]]}")
+        excused = np.flatnonzero(~good & (nt != 0))
+        if excused.size:
+            print(f"{what}: {excused.size}/{F} near-tie frames differ (excused)", flush=True)
+        far = excused[~close[excused]]
+        assert far.size == 0, (f"{what}: near-tie frames {far[:8]} chose metrics "
+                               f"{pm_g[far[:4]]} vs oracle {pm_o[far[:4]]}")
+        limit = max(1, F // 100) if max_excused is None else max_excused
+        assert excused.size <= limit, f"{what}: {excused.size} excused frames > {limit}"
         exact = same_u & same_ok & (pm_g == pm_o)
         return int(exact.sum())
     pm_g = pm_g.astype(np.int64)

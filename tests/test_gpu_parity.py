@@ -186,6 +186,50 @@ def test_degenerate_inputs(dtype):
             compare(g, o, dtype, f"{name} L={L}")
 
 
+@pytest.mark.parametrize("dtype", ["i8", "i16"])
+def test_input_below_minus_q_reads_as_minus_q(dtype):
+    """The integer domain is [-Q, Q]: an input of -Q - 1 (-128 / -32768) is
+    saturated to -Q on load, by the kernel as by the oracle.  Frames with
+    such values at every seventh position (channel F, G and leaves all read
+    them), at the headline code and a code whose root is a Rate-1 leaf."""
+    Q = 127 if dtype == "i8" else 32767
+    for N, K, r, poly, d, L in ((2048, 1723, 32, synth.CRC32_POLY, 4.0, 32),
+                                (256, 128, 8, synth.CRC8_POLY, 2.5, 8),
+                                (64, 64, 8, synth.CRC8_POLY, 2.5, 4)):
+        code, b = batch(N, K, r, poly, d, 24, 3.0, (11, N), dtype)
+        llr = b.llr.copy()
+        llr[:, ::7] = -Q - 1
+        llr[::3, 1::5] = -Q - 1
+        _say(f"({N},{K}) L={L} {dtype} with {-Q - 1} inputs")
+        g = gpu_decode(code, L, llr, dtype)
+        o = oracle_decode(code, L, llr, dtype)
+        compare(g, o, dtype, f"({N},{K}) {dtype} -Q-1 inputs")
+        o2 = oracle_decode(code, L, np.maximum(llr, -Q).astype(llr.dtype), dtype)
+        compare(g, o2, dtype, f"({N},{K}) {dtype} as -Q")
+
+
+def test_negative_zero_inputs():
+    """float32 -0.0 decides 0 (eq. (sc:h) compares alpha < 0): all -0.0
+    frames, and +/-2.0 frames with -0.0 sprinkled in, against the oracle,
+    including codes whose root is one leaf."""
+    rng = np.random.default_rng(12)
+    cases = [(synth.make_code(256, 128, 8, synth.CRC8_POLY, 2.5), 4, 4)]
+    for N, frozen in ((8, []), (4, [0]), (8, [0, 1, 2, 3, 4, 5, 6]), (32, list(range(16)))):
+        fz = np.zeros(N, np.uint8)
+        fz[frozen] = 1
+        cases.append((synth.PolarCode(N=N, K=N - len(frozen), r=0, poly=0, design_ebn0_db=0.0,
+                                      frozen=fz), 4, N))
+    for code, L, spc_max in cases:
+        llr = np.where(rng.random((40, code.N)) < 0.5, 2.0, -2.0).astype(np.float32)
+        llr[rng.random((40, code.N)) < 0.3] = -0.0
+        llr[:4] = -0.0
+        for LL in (1, L):
+            _say(f"-0.0 frames ({code.N},{code.K}) L={LL}")
+            g = gpu_decode(code, LL, llr, "f32", spc_max=spc_max)
+            o = oracle_decode(code, LL, llr, "f32", spc_max=spc_max)
+            compare(g, o, "f32", f"-0.0 ({code.N},{code.K}) L={LL}", max_excused=0)
+
+
 def test_deterministic():
     code, b = batch(2048, 1723, 32, synth.CRC32_POLY, 4.0, 128, 3.5, 7, "f32")
     g1 = gpu_decode(code, 32, b.llr, "f32")

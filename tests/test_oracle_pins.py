@@ -348,33 +348,48 @@ def test_rate0_metric_is_distance_to_zero_word(orc):
 # Special cases and equivalences
 # --------------------------------------------------------------------------
 
-def _fast_ssc(a, frozen):
-    """Textbook single-path Fast-SSC (Sec. II-C): Rate-0 -> zeros, Rate-1 ->
-    hard decision (eq. (info)), repetition -> sign of the sum (eq. (rep)),
-    SPC -> hard decision with the least reliable bit fixing the parity
-    (eq. (spc)).  Integer LLRs, int16 saturation in G."""
+def _fast_ssc(a, frozen, Q=32767, stats=None):
+    """Textbook single-path Fast-SSC (Sec. II-C) on integer LLRs saturated to
+    [-Q, Q]: Rate-0 -> zeros, Rate-1 -> hard decision (eq. (info)),
+    repetition -> sign of the sum (eq. (rep)), SPC -> hard decision with the
+    least reliable bit fixing the parity (eq. (spc)).  Returns (x, pm): the
+    codeword and its path metric, minus the summed leaf penalties
+    |alpha_i| [x_i != h(alpha_i)] of eq. (pm).  Q=None: no saturation.
+    stats["sat"] counts G results that had to be saturated."""
+    a = np.asarray(a, dtype=np.int64)
     nv = len(a)
     nf = int(frozen.sum())
+
+    def pen(x):
+        return -int(np.sum(np.abs(a) * (x != (a < 0))))
+
     if nv == 1:
-        return np.array([0 if nf else int(a[0] < 0)], np.uint8)
+        x = np.array([0 if nf else int(a[0] < 0)], np.uint8)
+        return x, pen(x)
     if nf == nv:
-        return np.zeros(nv, np.uint8)
+        x = np.zeros(nv, np.uint8)
+        return x, pen(x)
     if nf == 0:
-        return (a < 0).astype(np.uint8)
+        return (a < 0).astype(np.uint8), 0
     if nf == nv - 1 and not frozen[-1]:
-        return np.full(nv, 0 if a.sum() >= 0 else 1, np.uint8)
+        x = np.full(nv, 0 if a.sum() >= 0 else 1, np.uint8)
+        return x, pen(x)
     if nf == 1 and frozen[0] and nv == 4:
-        hd = (a < 0).astype(np.uint8)
-        if hd.sum() % 2:
-            hd[int(np.argmin(np.abs(a)))] ^= 1
-        return hd
+        x = (a < 0).astype(np.uint8)
+        if x.sum() % 2:
+            x[int(np.argmin(np.abs(a)))] ^= 1
+        return x, pen(x)
     h = nv // 2
     x, y = a[:h], a[h:]
     al = np.sign(x) * np.sign(y) * np.minimum(np.abs(x), np.abs(y))
-    bl = _fast_ssc(al, frozen[:h])
-    ar = np.clip(y + np.where(bl == 1, -x, x), -32767, 32767)
-    br = _fast_ssc(ar, frozen[h:])
-    return np.concatenate([bl ^ br, br])
+    bl, pl = _fast_ssc(al, frozen[:h], Q, stats)
+    ar = y + np.where(bl == 1, -x, x)
+    if Q is not None:
+        if stats is not None:
+            stats["sat"] = stats.get("sat", 0) + int(np.sum(np.abs(ar) > Q))
+        ar = np.clip(ar, -Q, Q)
+    br, pr = _fast_ssc(ar, frozen[h:], Q, stats)
+    return np.concatenate([bl ^ br, br]), pl + pr
 
 
 def test_list_of_one_is_fast_ssc(orc):
@@ -382,9 +397,110 @@ def test_list_of_one_is_fast_ssc(orc):
     b = synth.make_batch(code, 60, 1.5, 9, "i16")
     u, ok, pm, _ = orc.decode_tree(256, 128, code.frozen, code.poly, 8, 1, b.llr, "i16")
     for f in range(b.F):
-        x = _fast_ssc(b.llr[f].astype(np.int64), code.frozen)
+        x, p = _fast_ssc(b.llr[f], code.frozen)
         uu = orc.polar_transform(x)
         assert (uu[code.info_pos] == u[f]).all()
+        assert pm[f] == p
+
+
+def _saturating_frames(dtype, N, F, seed):
+    """Integer frames whose G results leave [-Q, Q] all the time: int8 at the
+    headline quantisation (scale 4) of a high-SNR channel plus uniform
+    full-range frames; int16 full-range frames (|G| up to 65534).  Some
+    frames carry the one value below -Q (-128 / -32768)."""
+    rng = np.random.default_rng(seed)
+    Q = 127 if dtype == "i8" else 32767
+    nt = np.int8 if dtype == "i8" else np.int16
+    out = rng.integers(-Q, Q + 1, (F, N))
+    if dtype == "i8":
+        y = 1.0 - 2.0 * rng.integers(0, 2, (F // 2, N)) + 0.45 * rng.normal(size=(F // 2, N))
+        out[: F // 2] = np.clip(np.rint(4 * 2 * y / 0.45 ** 2), -Q, Q)
+    out[F - 4:, ::7] = -Q - 1
+    return out.astype(nt)
+
+
+@pytest.mark.parametrize("dtype", ["i8", "i16"])
+def test_integer_saturation_pinned_by_fast_ssc(orc, dtype):
+    """G saturates every integer result to [-Q, Q] (Q = 127 / 32767), and a
+    channel value of -Q - 1 is read as -Q.  At L = 1 the list decoder is
+    Fast-SSC, whose decisions and metric (eq. (pm)) depend on the saturated
+    magnitudes: the oracle must equal the reference with bound Q on every
+    frame, while a bound of Q + 1 or no bound gives other results on some of
+    these frames, so a wrong bound in the oracle cannot pass."""
+    Q = 127 if dtype == "i8" else 32767
+    wrong_bound = {Q + 1: 0, None: 0}
+    for N, K in ((256, 128), (128, 64), (64, 32), (64, 40), (1024, 860)):
+        code = synth.make_code(N, K, 0, 0, 2.0 if K <= N // 2 else 4.0)
+        llr = _saturating_frames(dtype, N, 24, (N, K, Q))
+        u, ok, pm, _ = orc.decode_tree(N, K, code.frozen, 0, 0, 1, llr, dtype)
+        stats = {}
+        for f in range(llr.shape[0]):
+            a = np.maximum(llr[f].astype(np.int64), -Q)  # -Q - 1 read as -Q
+            x, p = _fast_ssc(a, code.frozen, Q, stats)
+            assert (orc.polar_transform(x)[code.info_pos] == u[f]).all(), (N, f)
+            assert pm[f] == p, (N, f, pm[f], p)
+            for alt in wrong_bound:
+                xa, pa = _fast_ssc(a, code.frozen, alt)
+                wrong_bound[alt] += int(pa != p or (xa != x).any())
+        assert stats["sat"] > 100, stats  # the inputs really saturate
+        # the -Q - 1 inputs are read as -Q
+        u2, _, pm2, _ = orc.decode_tree(N, K, code.frozen, 0, 0, 1,
+                                        np.maximum(llr, -Q).astype(llr.dtype), dtype)
+        assert (u2 == u).all() and (pm2 == pm).all()
+    assert min(wrong_bound.values()) >= 5, wrong_bound
+
+
+def test_final_pick_hand_frames(orc):
+    """Sec. II-B: the output is the best-metric path that passes the CRC, and
+    when none passes the best-metric path with crc_ok = 0.  Frames worked out
+    by hand in tests/golden/crc_pick_hand_frames.txt (a (4,4) code whose root
+    is one Rate-1 node, CRC-2)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "crc_pick_hand_frames.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    assert len(rows) >= 3
+    frozen = np.zeros(4, np.uint8)
+    for row in rows:
+        L = int(row[0])
+        llr = [int(v) for v in row[1:5]]
+        u_want = [int(v) for v in row[5]]
+        ok_want, pm_want = int(row[6]), int(row[7])
+        for dtype in ("i8", "i16", "f32"):
+            a = np.array(llr, dtype={"i8": np.int8, "i16": np.int16, "f32": np.float32}[dtype])
+            u, ok, pm, _ = orc.decode_tree(4, 4, frozen, 0x3, 2, L, a, dtype)
+            assert list(u[0]) == u_want and ok[0] == ok_want and pm[0] == pm_want, (row, dtype)
+
+
+def test_negative_zero_decides_zero(orc):
+    """eq. (sc:h): the hard decision is 1 exactly when alpha < 0, so an LLR
+    of -0.0 decides 0 (a sign-bit decision would decide 1).  The all-zero
+    codeword received as exact -0.0 values (G of two -0.0 stays -0.0, so the
+    zeros reach the leaves along right branches), or as +2.0 with some
+    values -0.0 at the input of a code whose root is one leaf (Rate-1,
+    SPC, repetition), decodes to u = 0 with metric 0."""
+    code = synth.make_code(256, 128, 8, synth.CRC8_POLY, 2.5)
+    llr = np.full((1, 256), -0.0, np.float32)
+    for L in (1, 4):
+        for mode in (0, 1):
+            u, ok, pm, _ = orc.decode_tree(256, 128, code.frozen, code.poly, 8, L, llr, "f32",
+                                           mode=mode)
+            assert (u == 0).all() and ok.all() and (pm == 0).all(), (L, mode)
+    u, ok, pm, _ = orc.decode_scl(256, 128, code.frozen, code.poly, 8, 4, llr, "f32")
+    assert (u == 0).all() and ok.all() and (pm == 0).all()
+    rng = np.random.default_rng(0)
+    for N, frozen in ((8, []), (4, [0]), (8, [0, 1, 2, 3, 4, 5, 6])):
+        fz = np.zeros(N, np.uint8)
+        fz[frozen] = 1
+        K = N - len(frozen)
+        x = np.full((6, N), 2.0, np.float32)
+        for f in range(6):
+            x[f, rng.choice(N, f % N + 1, replace=False)] = -0.0
+        for L in (1, 2, 4):
+            u, ok, pm, _ = orc.decode_tree(N, K, fz, 0, 0, L, x, "f32", spc_max=N)
+            assert (u == 0).all() and (pm == 0).all(), (N, L)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "i16", "i8"])
