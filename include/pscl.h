@@ -196,6 +196,26 @@ pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8
                         uint8_t* crc_ok, void* pm, void* stream);
 
 /*
+ * pscl_decode for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs and errors as pscl_decode, but the plan's own
+ * workspace is never used or allocated: the frame counter and the global
+ * workspaces live in one static device array of the library, 128 MiB per
+ * device (the counter in its first 256 bytes), held from the library's load
+ * until the process ends.  The launch uses as many workgroups as have a
+ * workspace there, at most the plan's own count, so a plan whose levels
+ * spill to the workspace may run on fewer workgroups than pscl_decode uses.
+ * Issues kernel launches only (no allocation, copy or memset).
+ * Returns PSCL_E_UNSUPPORTED when one workgroup's workspace alone exceeds
+ * 128 MiB - 256 bytes, PSCL_E_INVALID when the current device is not the
+ * plan's.  Every call on a device shares that device's array, which keeps
+ * the last call's contents: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.
+ */
+pscl_status pscl_decode_noalloc(const pscl_plan* plan, const void* llr, int64_t F,
+                                uint8_t* u_hat, uint8_t* crc_ok, void* pm, void* stream);
+
+/*
  * One-call form decode(N, K, frozen_mask, crc_poly, L, llr) -> u_hat: builds
  * (or reuses from a per-process cache keyed by every argument that shapes the
  * plan) the plan for the Dec-SPC-4 tree, with a group of it holding two

@@ -87,6 +87,8 @@ def _load():
     lib.pscl_plan_reserve.restype = c_int
     lib.pscl_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp]
     lib.pscl_decode.restype = c_int
+    lib.pscl_decode_noalloc.argtypes = [vp, vp, c_i64, vp, vp, vp, vp]
+    lib.pscl_decode_noalloc.restype = c_int
     lib.pscl_decode_oneshot.argtypes = [c_int, c_int, u8p, c_u64, c_int, c_int, c_int, vp, c_i64,
                                         vp, vp, vp]
     lib.pscl_decode_oneshot.restype = c_int
@@ -232,6 +234,18 @@ class Plan:
                              device=self.device)
         _check(lib.pscl_decode(self._h, llr.data_ptr(), F, u_hat.data_ptr(), crc_ok.data_ptr(),
                                pm.data_ptr(), _stream_handle(self.device)), "pscl_decode")
+        return u_hat, crc_ok, pm
+
+    def decode_noalloc(self, llr, u_hat, crc_ok, pm):
+        """pscl_decode_noalloc into caller-provided outputs: the library's
+        static device scratch instead of the plan's workspace (no device
+        allocation; overlapping calls on one device race)."""
+        if llr.device != self.device or not llr.is_contiguous() or llr.shape[1] != self.N:
+            raise ValueError(f"llr must be a contiguous F x {self.N} tensor on the plan's device")
+        F = llr.shape[0]
+        _check(lib.pscl_decode_noalloc(self._h, llr.data_ptr(), F, u_hat.data_ptr(),
+                                       crc_ok.data_ptr(), pm.data_ptr(),
+                                       _stream_handle(self.device)), "pscl_decode_noalloc")
         return u_hat, crc_ok, pm
 
     def close(self):

@@ -1956,6 +1956,13 @@ __global__ void __launch_bounds__(1024)
 
 __global__ void zero_counter(unsigned long long* counter) { *counter = 0ull; }
 
+// Device memory of pscl_decode_noalloc: the frame counter in the first 256
+// bytes, then the global workspaces of as many workgroups as fit.  One copy
+// per device, held from the library's load until the process ends.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr size_t kScratchHead = 256;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 // ---------------------------------------------------------------------------
 // Adaptive decoding (Sec. VI): after a single-path pass over every frame,
 // the frames whose CRC failed are gathered and list-decoded again.
@@ -2152,24 +2159,27 @@ const void* kernel_for(int dtype, int L) {
     return wide_list(L) ? kernel_for_t<true>(dtype) : kernel_for_t<false>(dtype);
 }
 
+// One decode_kernel launch of plan p with kernel arguments a (a.ws: the
+// workspaces of `grid` workgroups) and frame counter `counter`.
 template <bool W>
-void launch_decode(const pscl_plan* p, int grid, hipStream_t s, const void* llr, int64_t F,
-                   uint8_t* u_hat, uint8_t* crc_ok, void* pm) {
+void launch_decode(const pscl_plan* p, const KArgs& a, unsigned long long* counter, int grid,
+                   hipStream_t s, const void* llr, int64_t F, uint8_t* u_hat, uint8_t* crc_ok,
+                   void* pm) {
     switch (p->dtype) {
         case PSCL_F32:
             hipLaunchKernelGGL((decode_kernel<float, W>), dim3(grid), dim3(p->NT), p->lds_bytes, s,
-                               p->args, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat,
-                               crc_ok, pm, p->d_counter);
+                               a, (const uint64_t*)p->d_ops, (const float*)llr, F, u_hat, crc_ok,
+                               pm, counter);
             break;
         case PSCL_I16:
             hipLaunchKernelGGL((decode_kernel<int16_t, W>), dim3(grid), dim3(p->NT), p->lds_bytes,
-                               s, p->args, (const uint64_t*)p->d_ops, (const int16_t*)llr, F,
-                               u_hat, crc_ok, pm, p->d_counter);
+                               s, a, (const uint64_t*)p->d_ops, (const int16_t*)llr, F, u_hat,
+                               crc_ok, pm, counter);
             break;
         default:
             hipLaunchKernelGGL((decode_kernel<int8_t, W>), dim3(grid), dim3(p->NT), p->lds_bytes,
-                               s, p->args, (const uint64_t*)p->d_ops, (const int8_t*)llr, F,
-                               u_hat, crc_ok, pm, p->d_counter);
+                               s, a, (const uint64_t*)p->d_ops, (const int8_t*)llr, F, u_hat,
+                               crc_ok, pm, counter);
             break;
     }
 }
@@ -2366,6 +2376,24 @@ static pscl_status ensure_workspace(const pscl_plan* p) {
     if (st != PSCL_OK) return st;
     p->d_ws = ws;
     p->args.ws = ws;
+    return PSCL_OK;
+}
+
+// Device address of `scratch` on device dev (current), looked up once per
+// device: host code never uses the symbol's name as an address.
+static pscl_status scratch_base(int dev, uint8_t** out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static uint8_t* base[kMaxDev] = {};
+    if (dev < 0 || dev >= kMaxDev) return PSCL_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!base[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return PSCL_E_HIP;
+        base[dev] = (uint8_t*)ptr;
+    }
+    *out = base[dev];
     return PSCL_OK;
 }
 
@@ -2589,8 +2617,44 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     // the frame counter starts at zero (a one-thread kernel, so that the
     // call can be captured in a graph)
     hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, p->d_counter);
-    if (wide_list(p->L)) launch_decode<true>(p, grid, s, llr, F, u_hat, crc_ok, pm);
-    else launch_decode<false>(p, grid, s, llr, F, u_hat, crc_ok, pm);
+    if (wide_list(p->L))
+        launch_decode<true>(p, p->args, p->d_counter, grid, s, llr, F, u_hat, crc_ok, pm);
+    else
+        launch_decode<false>(p, p->args, p->d_counter, grid, s, llr, F, u_hat, crc_ok, pm);
+    e = hipGetLastError();
+    return e == hipSuccess ? PSCL_OK : PSCL_E_HIP;
+}
+
+pscl_status pscl_decode_noalloc(const pscl_plan* p, const void* llr, int64_t F, uint8_t* u_hat,
+                                uint8_t* crc_ok, void* pm, void* stream) {
+    if (!p || F < 0) return PSCL_E_INVALID;
+    if (F == 0) return PSCL_OK;
+    if (!llr || !u_hat) return PSCL_E_INVALID;
+    if (((uintptr_t)llr & 15u) != 0) return PSCL_E_INVALID;  // 16-byte vector loads
+    // the workspace of one workgroup must fit beside the counter
+    const int64_t room = (int64_t)(kScratchBytes - kScratchHead);
+    if (p->args.ws_frame > room) return PSCL_E_UNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_HIP;
+    if (dev != p->device) return PSCL_E_INVALID;
+    uint8_t* base = nullptr;
+    const pscl_status st = scratch_base(dev, &base);
+    if (st != PSCL_OK) return st;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return PSCL_E_HIP;
+    // as many workgroups as have a workspace in the scratch (the frame
+    // counter hands every frame to one of them)
+    int64_t grid = std::min<int64_t>(F, p->grid_max);
+    if (p->args.ws_frame > 0) grid = std::min<int64_t>(grid, room / p->args.ws_frame);
+    KArgs a = p->args;
+    a.ws = base + kScratchHead;
+    unsigned long long* counter = (unsigned long long*)base;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, counter);
+    if (wide_list(p->L))
+        launch_decode<true>(p, a, counter, (int)grid, s, llr, F, u_hat, crc_ok, pm);
+    else
+        launch_decode<false>(p, a, counter, (int)grid, s, llr, F, u_hat, crc_ok, pm);
     e = hipGetLastError();
     return e == hipSuccess ? PSCL_OK : PSCL_E_HIP;
 }
