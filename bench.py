@@ -94,6 +94,74 @@ def recorded_traffic(dtype):
     return float(vals[key]) if key in vals else None
 
 
+def recorded_counters(dtype):
+    """Per-frame SQ counters of the decode kernel from the committed
+    rocprofv3 summary (instructions per frame, LDS bank-conflict cycles per
+    LDS-active cycle), or None when that summary was taken on a different
+    kernel source."""
+    path = os.path.join(ROOT, "profiles", "decode_kernel_2048_1723_L32_counters.txt")
+    if not os.path.exists(path):
+        return None
+    src, rows = None, {}
+    col = {"f32": 2, "i8": 4}.get(dtype)
+    for line in open(path):
+        if "sha256/16" in line and ":" in line:
+            src = line.rsplit(":", 1)[1].strip()
+        parts = [x.strip() for x in line.split("|")]
+        if col is not None and len(parts) == 5 and parts[0].startswith(("SQ_", "GRBM_")):
+            rows[parts[0]] = float(parts[col])
+    if src != kernel_source_hash() or not rows:
+        return None
+    out = {k.lower() + "_per_frame": v for k, v in rows.items()
+           if k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_BRANCH")}
+    if rows.get("SQ_ACTIVE_INST_LDS"):
+        out["lds_bank_conflict_per_lds_active_cycle"] = round(
+            rows["SQ_LDS_BANK_CONFLICT"] / rows["SQ_ACTIVE_INST_LDS"], 3)
+    return out
+
+
+ELEM = {"f32": 4, "i16": 2, "i8": 1}
+PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12  # 128 B per clock per CU: 78.6 TB/s
+PEAK_HBM_GBS = 8000.0
+
+
+def roofline_terms(wk, N, K, dtype, frames_per_s, hbm_measured=None):
+    """The three bounds of the path for one kernel (per-frame algorithmic
+    figures times frames per second against each peak):
+      alu        F + G outputs, leaf reads and candidates as element
+                 operations against one 32-bit VALU lane-op per element per
+                 clock (39.3 T/s); the integer paths issue packed 16-bit
+                 operations (two elements per lane-op), so their peak is
+                 doubled;
+      lds_model  (F + G) x 3 + leaf reads elements of the dtype's size (an
+                 operation reads two values and writes one) against 128 B
+                 per clock per CU of LDS (78.6 TB/s);
+      hbm        the algorithmic bytes (LLR row in, decided bits out) and,
+                 when recorded for this source, the measured HBM bytes
+                 against 8 TB/s."""
+    es = ELEM[dtype]
+    alu_peak = PEAK_ELEM_OPS * (1 if dtype == "f32" else 2) / 1e12
+    alu = wk["total"] * frames_per_s / 1e12
+    lds_b = ((wk["F"] + wk["G"]) * 3 + wk["leaf_reads"]) * es
+    lds = lds_b * frames_per_s / 1e12
+    hbm_b = N * es + K
+    hbm = hbm_b * frames_per_s / 1e9
+    t = {"alu": {"achieved": round(alu, 4), "peak": round(alu_peak, 2), "unit": "Telem-op/s",
+                 "frac": round(alu / alu_peak, 5)},
+         "lds_model": {"bytes_per_frame": lds_b, "achieved": round(lds, 4),
+                       "peak": round(PEAK_LDS_TBS, 2), "unit": "TB/s",
+                       "frac": round(lds / PEAK_LDS_TBS, 5)},
+         "hbm_algorithmic": {"bytes_per_frame": hbm_b, "achieved": round(hbm, 2),
+                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(hbm / PEAK_HBM_GBS, 5)}}
+    if hbm_measured is not None:
+        m = hbm_measured * frames_per_s / 1e9
+        t["hbm_measured"] = {"bytes_per_frame": round(hbm_measured), "achieved": round(m, 1),
+                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(m / PEAK_HBM_GBS, 5)}
+    return t
+
+
 def wilson(k, n, z=1.959964):
     """Wilson score 95% interval of a binomial proportion k / n."""
     if n == 0:
@@ -157,20 +225,40 @@ def mixed_leg(pk, torch, synth, frames_per_code=1456, reps=3):
                         "BPSK-AWGN at each code's design Eb/N0"}
 
 
+def quantile_ci(x, q, z=1.959964):
+    """Distribution-free 95% interval of the q-quantile from order statistics
+    (binomial ranks n q -+ z sqrt(n q (1 - q))); it assumes independent
+    samples, which queueing latencies are not, so it is optimistic."""
+    import numpy as np
+
+    v = np.sort(np.asarray(x, dtype=np.float64))
+    n = v.size
+    if n == 0:
+        return (None, None)
+    h = z * (n * q * (1 - q)) ** 0.5
+    lo = int(max(0, np.floor(n * q - h)))
+    hi = int(min(n - 1, np.ceil(n * q + h)))
+    return (round(float(v[lo]), 1), round(float(v[hi]), 1))
+
+
 def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), span_s=0.25,
                 max_requests=16000, streams=4):
     """Poisson arrivals of requests of 1..64 frames of a random code of the
-    mixed set (int8), replayed through a server and as plain per-request
-    launches; p50 / p99 latency and sustained payload Gbps."""
+    mixed set (int8), replayed through a server on `streams` streams and as
+    plain per-request launches round-robin on as many streams (a set of
+    plans per stream); p50 / p99 latency (with order-statistic intervals)
+    and sustained payload Gbps."""
     codes = c4_codes(synth)
-    plans, pool = [], []
+    sets = [[pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8")
+             for code, L, _ in codes] for _ in range(streams)]
+    plans = sets[0]
+    pool = []
     for i, (code, L, d) in enumerate(codes):
-        plans.append(pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8"))
         b = synth.make_batch(code, 64, d, (5, i), "i8")
         pool.append(torch.from_numpy(b.llr).cuda())
     payload = [c.K - c.r for c, _, _ in codes]
     rng = np.random.default_rng(2015)
-    out = {}
+    out = {"streams": streams, "span_s": span_s, "max_requests": max_requests}
     for lam in rates:
         n = int(min(max_requests, lam * span_s))
         idx = rng.integers(len(codes), size=n)
@@ -178,43 +266,60 @@ def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), s
         arrivals = np.cumsum(rng.exponential(1e6 / lam, n))
         work = [(int(i), pool[int(i)][: int(f)]) for i, f in zip(idx, F)]
         bits = float(sum(payload[int(i)] * int(f) for i, f in zip(idx, F)))
-        row = {"requests": n}
-        for name, sv in (("server", pk.Server(plans, streams=streams)), ("per_request", None)):
-            _, lat, el = pk.replay(plans, work, arrivals, server=sv)
+        row = {"requests": n, "arrival_span_s": round(float(arrivals[-1]) * 1e-6, 4)}
+        for name in ("server", "per_request"):
+            if name == "server":
+                sv = pk.Server(plans, streams=streams)
+                _, lat, el = pk.replay(plans, work, arrivals, server=sv)
+            else:
+                sv = None
+                _, lat, el = pk.replay([p for st in sets for p in st], work, arrivals,
+                                       streams=streams)
             torch.cuda.synchronize()
             row[name] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
                          "p99_us": round(float(np.percentile(lat, 99)), 1),
+                         "p99_ci95_us": quantile_ci(lat, 0.99),
                          "gbps": round(bits / el / 1e3, 4)}
             if sv is not None:
                 row[name]["launches"] = sv.stats()["launches"]
                 sv.close()
         out[f"{int(lam)}"] = row
+    for st in sets:
+        for p in st:
+            p.close()
     return out
 
 
-def adaptive_leg(pk, torch, np, synth, code, b, frames, dtypes=("f32", "i8"), steps=5):
-    """Adaptive decoding (L = 1 first, L = 32 for the frames whose CRC fails)
-    on the headline frames: info Gbps and the share of frames list-decoded."""
+def adaptive_leg(pk, torch, code, frames, points=(3.5, 4.0, 4.5), dtypes=("f32", "i8"),
+                 steps=3, seed=0x41444150):
+    """Adaptive decoding (Sec. VI, Table 2): L = 1 first, L = 32 for the
+    frames whose CRC fails, on device-made frames at each Eb/N0; info Gbps,
+    the share of frames list-decoded and the FER."""
     out = {}
     for dtype in dtypes:
-        host = synth.quantize(b.llr_f32, dtype)
-        llr = torch.from_numpy(host).cuda()
+        gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, dtype)
         fast = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 1, dtype)
         lst = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 32, dtype)
         ad = pk.Adaptive(fast, lst, max_frames=frames)
-        u, ok, pm, n_list = ad.decode(llr)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            ad.decode(llr, u, ok, pm, n_list)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        out[dtype] = {"gbps": round(frames * PAYLOAD / (ms * 1e-3) / 1e9, 4), "ms": round(ms, 3),
-                      "list_decoded": int(n_list.item()),
-                      "fer": float((u.cpu().numpy() != b.info).any(axis=1).mean())}
+        rows = {}
+        for e in points:
+            llr, info = gen.generate(frames, e, seed)
+            u, ok, pm, n_list = ad.decode(llr)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                ad.decode(llr, u, ok, pm, n_list)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            rows[str(e)] = {"gbps": round(frames * PAYLOAD / (ms * 1e-3) / 1e9, 4),
+                            "ms": round(ms, 3), "list_decoded": int(n_list.item()),
+                            "fer": float((u != info).any(dim=1).float().mean().item())}
+        out[dtype] = rows
         ad.close()
+        gen.close()
+    out["frames"] = frames
     return out
 
 
@@ -321,6 +426,74 @@ def crc_length_leg(pk, torch, synth, frames_per_point, points=(2.0, 2.5, 3.0, 3.
     return out
 
 
+def c3_leg(pk, torch, synth, frames=65536, lists=(2, 4, 8, 16, 32), dtypes=("i16", "f32"),
+           ebn0=4.0, steps=3, seed=0x43330001):
+    """Throughput against list size on the (1024,860) CRC-32 code
+    (construction at 4.0 dB, frames made on the device at 4.0 dB): payload
+    Gbps and FER per L and dtype."""
+    code = synth.make_code(1024, 860, 32, synth.CRC32_POLY, 4.0)
+    out = {"code": "(1024,860) CRC-32 inside K", "ebn0_db": ebn0, "frames": frames}
+    for dtype in dtypes:
+        gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, dtype)
+        llr, info = gen.generate(frames, ebn0, seed)
+        rows = {}
+        for L in lists:
+            plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, dtype)
+            u, ok, pm = plan.decode(llr)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                plan.decode(llr, u, ok, pm)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            rows[f"L{L}"] = {"gbps": round(frames * code.payload / (ms * 1e-3) / 1e9, 4),
+                             "ms": round(ms, 3),
+                             "fer": float((u != info).any(dim=1).float().mean().item())}
+            plan.close()
+        out[dtype] = rows
+        gen.close()
+    return out
+
+
+def copy_inclusive_leg(pk, torch, synth, code, b, frames, dtypes=("f32", "i8"), steps=3):
+    """The timed decode with the host copies the paper's latencies include
+    (Sec. VII-A): LLRs from pinned host memory to the device, decoding, and
+    decided bits and CRC flags back to pinned host memory, all on one
+    stream; payload Gbps of the whole."""
+    out = {}
+    for dtype in dtypes:
+        host = torch.from_numpy(synth.quantize(b.llr_f32, dtype)).pin_memory()
+        plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, 32, dtype)
+        llr = torch.empty_like(host, device="cuda")
+        u = torch.empty((frames, code.K), dtype=torch.uint8, device="cuda")
+        ok = torch.empty(frames, dtype=torch.uint8, device="cuda")
+        pm = torch.empty(frames, dtype=torch.float32 if dtype == "f32" else torch.int32,
+                         device="cuda")
+        u_h = torch.empty((frames, code.K), dtype=torch.uint8).pin_memory()
+        ok_h = torch.empty(frames, dtype=torch.uint8).pin_memory()
+
+        def step():
+            llr.copy_(host, non_blocking=True)
+            plan.decode(llr, u, ok, pm)
+            u_h.copy_(u, non_blocking=True)
+            ok_h.copy_(ok, non_blocking=True)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[dtype] = {"gbps": round(frames * PAYLOAD / (ms * 1e-3) / 1e9, 4), "ms": round(ms, 3),
+                      "h2d_bytes": int(host.numel() * host.element_size()),
+                      "d2h_bytes": int(frames * (code.K + 1))}
+        plan.close()
+    return out
+
+
 def graph_leg(pk, torch, synth, code, b, frames=64, calls=64, dtype="i8", reps=5):
     """Many small decodes (calls x frames of the headline code, L = 32):
     issued one by one, or captured once in a HIP graph and replayed.
@@ -374,12 +547,19 @@ def graph_leg(pk, torch, synth, code, b, frames=64, calls=64, dtype="i8", reps=5
             "graph_equals_eager": same}
 
 
-def cpu_threads():
+def host_cpus():
+    """(CPUs this process may run on, CPUs the host reports)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    return n, os.cpu_count() or n
+
+
+def cpu_threads():
+    """Oracle threads: every CPU this process may use, at most 16 (the CPU
+    share one GPU's jobs get on a shared host)."""
+    return max(1, min(host_cpus()[0], 16))
 
 
 def main():
@@ -400,6 +580,13 @@ def main():
     ap.add_argument("--no-spc-plus", action="store_true", help="skip the SPC-4 vs SPC-4+ leg")
     ap.add_argument("--no-fer-sweep", action="store_true", help="skip the FER sweep leg")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--no-copies", action="store_true", help="skip the copy-inclusive timing")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the (1024,860) throughput-against-L leg")
+    ap.add_argument("--serving-span", type=float, default=0.25,
+                    help="seconds of Poisson arrivals per rate in the serving leg")
+    ap.add_argument("--serving-max-requests", type=int, default=16000,
+                    help="requests per rate at most in the serving leg")
     ap.add_argument("--no-crc-study", action="store_true",
                     help="skip the CRC-length study (1024,860) at L=128")
     ap.add_argument("--crc-study-frames", type=int, default=1 << 19,
@@ -478,21 +665,28 @@ def main():
     achieved = wk["total"] * args.frames / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_ELEM_OPS / 1e12
     tpf = recorded_traffic(args.dtype)
+    fps = args.frames / (kernel_ms * 1e-3)
+    terms = roofline_terms(wk, N, K, args.dtype, fps, tpf)
     roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(peak, 2),
             "unit": "Telem-op/s", "frac": round(achieved / peak, 5),
             "traffic": None if tpf is None else round(tpf * args.frames),
             "kernel": "pscl::decode_kernel", "kernel_ms": round(kernel_ms, 4),
             "elem_ops_per_frame": wk["total"], "frames_per_launch": args.frames,
+            "terms": terms,
+            "closest_to_peak": max(terms, key=lambda k: terms[k]["frac"]),
+            "counters": recorded_counters(args.dtype),
             "kernel_source": kernel_source_hash()}
     extra = {}
     for dtype, leg in legs.items():
         if dtype == args.dtype:
             continue
         ms2, kms2, u2, _, plan2, _ = leg
+        t2 = roofline_terms(wk, N, K, dtype, args.frames / (kms2 * 1e-3), recorded_traffic(dtype))
         extra[dtype] = {"value": round(args.frames * PAYLOAD / (ms2 * 1e-3) / 1e9, 4),
                         "ms_per_step": round(ms2, 4), "kernel_ms": round(kms2, 4),
                         "fer": float((u2 != b.info).any(axis=1).mean()),
                         "roofline_frac": round(wk["total"] * args.frames / (kms2 * 1e-3) / PEAK_ELEM_OPS, 5),
+                        "roofline_terms": t2, "counters": recorded_counters(dtype),
                         "launch": plan2.info()}
 
     cpu = None
@@ -512,7 +706,9 @@ def main():
         lo, hi = wilson(k_or, S)
         fer_cmp = {"frames": S, "oracle": k_or / S, "oracle_ci95": [round(lo, 6), round(hi, 6)],
                    "gpu": k_gpu / S, "gpu_inside_ci": bool(lo <= k_gpu / S <= hi)}
+        avail, nproc = host_cpus()
         cpu = {"value": round(S * PAYLOAD / (te - ts) / 1e9, 6), "unit": "Gbps", "cores": th,
+               "host_cpus_available": avail, "host_nproc": nproc,
                "kind": "oracle",
                "sample": f"first {S} frames of the timed batch, decoder A (tree, L=32, {args.dtype})",
                "seconds": round(te - ts, 3), "gpu_agrees_on_sample": f"{agree}/{S}",
@@ -526,7 +722,13 @@ def main():
                            "frames": S1, "seconds": round(t1, 3),
                            "us_per_frame": round(t1 / S1 * 1e6, 1)}
 
-    mixed = serving = adaptive = spc_plus = sweep = crc_study = graph = None
+    mixed = serving = adaptive = spc_plus = sweep = crc_study = graph = c3 = copies = None
+    if not args.single and not args.no_copies:
+        print("[bench] copy-inclusive timing", file=sys.stderr, flush=True)
+        copies = copy_inclusive_leg(pk, torch, synth, code, b, args.frames)
+    if not args.single and not args.no_c3:
+        print("[bench] (1024,860) throughput against L", file=sys.stderr, flush=True)
+        c3 = c3_leg(pk, torch, synth)
     if not args.single and not args.no_graph:
         print("[bench] small decodes: eager vs graph replay", file=sys.stderr, flush=True)
         graph = graph_leg(pk, torch, synth, code, b)
@@ -543,13 +745,14 @@ def main():
         spc_plus = spc_plus_leg(pk, torch, synth, code, b, args.frames)
     if not args.single and not args.no_adaptive:
         print("[bench] adaptive decoding", file=sys.stderr, flush=True)
-        adaptive = adaptive_leg(pk, torch, np, synth, code, b, args.frames)
+        adaptive = adaptive_leg(pk, torch, code, args.frames)
     if not args.single and not args.no_mixed:
         print("[bench] mixed launch vs per-code launches", file=sys.stderr, flush=True)
         mixed = mixed_leg(pk, torch, synth)
     if not args.single and not args.no_serving:
         print("[bench] serving replay", file=sys.stderr, flush=True)
-        serving = serving_leg(pk, torch, synth, np)
+        serving = serving_leg(pk, torch, synth, np, span_s=args.serving_span,
+                              max_requests=args.serving_max_requests)
 
     info = plan.info()
     out = {
@@ -584,6 +787,8 @@ def main():
         "fer_sweep": sweep,
         "crc_length_L128": crc_study,
         "graph_replay": graph,
+        "copy_inclusive": copies,
+        "throughput_vs_L_1024_860": c3,
         "mixed": mixed,
         "serving": serving,
     }

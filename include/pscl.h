@@ -28,9 +28,11 @@
  *
  * Ownership: the caller owns every device buffer passed in; a plan owns its
  * device schedule, tables and workspace.  Decoding is asynchronous on the
- * caller's HIP stream.  A plan's workspace is allocated by the first
- * pscl_decode on it (or by pscl_plan_reserve); later calls never allocate.
- * A plan's workspace serves one call at a time: calls on one plan must be
+ * caller's HIP stream.  A plan's workspace is allocated by pscl_decode
+ * for the workgroups a call needs (F frames use at most F) and enlarged when
+ * a later call needs more (to the next power of two workgroups, at most the
+ * full grid); pscl_plan_reserve allocates the full grid's, after which no
+ * call allocates.  A plan's workspace serves one call at a time: calls on one plan must be
  * ordered (one stream, or synchronised); a group (below) keeps a workspace
  * per call in flight, so its calls may overlap on different streams, and so
  * may calls of the one-call form.  All device pointers must be accessible
@@ -62,7 +64,8 @@ typedef enum {
     PSCL_E_NOMEM = 3,       /* device allocation failed */
     PSCL_E_HIP = 4,         /* HIP runtime error */
     PSCL_E_NODEV = 5,       /* no usable gfx950 device */
-    PSCL_E_BUSY = 6         /* a server holds as many requests as it admits */
+    PSCL_E_BUSY = 6,        /* a server holds as many requests as it admits */
+    PSCL_E_TIMEOUT = 7      /* a wait with a time limit ended before completion */
 } pscl_status;
 
 typedef enum { PSCL_F32 = 0, PSCL_I16 = 1, PSCL_I8 = 2 } pscl_dtype;
@@ -170,11 +173,16 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
 /* Release a plan (NULL allowed).  Synchronises the device first. */
 void pscl_plan_destroy(pscl_plan* plan);
 
-/* Allocate the plan's decoding workspace now (pscl_decode otherwise does
- * on its first call), so that every pscl_decode on it is free of
- * allocation, e.g. before capturing one in a HIP graph.  Plans used only
- * through groups or servers never need it.  Returns
- * PSCL_E_NOMEM when the device is out of memory. */
+/* Device bytes one frame of the plan occupies while it is decoded: its
+ * global workspace and LDS, its LLR row and its outputs (K + 1 + 4 bytes).
+ * Servers charge requests F times this against their admission budget. */
+pscl_status pscl_plan_footprint(const pscl_plan* plan, int64_t* bytes_per_frame);
+
+/* Allocate the plan's decoding workspace for its full grid now
+ * (pscl_decode otherwise allocates what its calls need), so that every
+ * pscl_decode on it is free of allocation, e.g. before capturing one in a
+ * HIP graph.  Plans used only through groups or servers never need it.
+ * Returns PSCL_E_NOMEM when the device is out of memory. */
 pscl_status pscl_plan_reserve(const pscl_plan* plan);
 
 /*
@@ -188,9 +196,10 @@ pscl_status pscl_plan_reserve(const pscl_plan* plan);
  *       PSCL_F32, int32 for the integer dtypes.
  *   stream: hipStream_t or NULL for the default stream.
  * F = 0 is a no-op.  Returns PSCL_E_INVALID on null required pointers or
- * F < 0.  Once the plan's workspace exists (pscl_plan_reserve, or any
- * earlier call) only kernel launches are issued (no allocation, copy or
- * memset), so a call can be captured in a HIP graph and replayed.
+ * F < 0.  When the plan's workspace already serves the call's workgroups
+ * (after pscl_plan_reserve, or an earlier call on at least as many frames,
+ * up to the full grid) only kernel launches are issued (no allocation, copy
+ * or memset), so a call can be captured in a HIP graph and replayed.
  */
 pscl_status pscl_decode(const pscl_plan* plan, const void* llr, int64_t F, uint8_t* u_hat,
                         uint8_t* crc_ok, void* pm, void* stream);
@@ -296,6 +305,12 @@ pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const 
  * Each request's results equal pscl_decode of it alone.  Latency runs from
  * submission (or, in pscl_replay, the scheduled arrival) to the moment the
  * dispatcher sees the launch that decoded it complete.
+ *
+ * Admission (pscl_server_submit returns PSCL_E_BUSY, the caller retries):
+ * by request count, by queued frames, and by device footprint: a request of
+ * F frames of plan p is charged F * pscl_plan_footprint(p) bytes from its
+ * submission to its completion, and the charges held stay within
+ * max_footprint_bytes.
  */
 typedef struct pscl_server pscl_server;
 
@@ -307,6 +322,7 @@ typedef struct {
     int64_t max_pending_frames; /* frames queued and not yet launched (0 = no limit) */
     int64_t max_batch_frames;   /* frames per launch (0 = no limit; one request at least) */
     int max_batch_requests;     /* requests per launch (0 = 1024) */
+    int64_t max_footprint_bytes; /* device bytes of held requests (0 = no limit) */
 } pscl_server_cfg;
 
 /* Create a server on the current device (allocates one group, stream and
@@ -319,13 +335,18 @@ void pscl_server_destroy(pscl_server* server);
 
 /*
  * Queue one request and return its ticket.  The job's buffers stay the
- * caller's and must stay valid until the request is done.  PSCL_E_BUSY when
- * the server already holds max_requests requests or the request would take
- * the queued frames beyond max_pending_frames (admission control: the
- * caller retries later); PSCL_E_INVALID for a bad job or one larger than
- * max_pending_frames.  A failed launch is reported by every later call.
+ * caller's and must stay valid until the request is done.  stream: the HIP
+ * stream (NULL = the null stream) whose work issued before this call
+ * produces the job's inputs; the request is decoded only after that work
+ * (an event recorded on it now).  PSCL_E_BUSY when the server already holds
+ * max_requests requests, or the request would take the queued frames beyond
+ * max_pending_frames or the held footprint beyond max_footprint_bytes
+ * (admission control: the caller retries later); PSCL_E_INVALID for a bad
+ * job or one that exceeds either limit alone.  A failed launch is reported
+ * by every later call.
  */
-pscl_status pscl_server_submit(pscl_server* server, const pscl_job* job, uint64_t* ticket);
+pscl_status pscl_server_submit(pscl_server* server, const pscl_job* job, void* stream,
+                               uint64_t* ticket);
 
 /* *done = 1 once the request's outputs are complete in device memory (and
  * its latency in microseconds to *latency_us when not NULL); a ticket is
@@ -333,8 +354,11 @@ pscl_status pscl_server_submit(pscl_server* server, const pscl_job* job, uint64_
 pscl_status pscl_server_poll(pscl_server* server, uint64_t ticket, int* done,
                              double* latency_us);
 
-/* Block until the request is done (then as pscl_server_poll). */
-pscl_status pscl_server_wait(pscl_server* server, uint64_t ticket, double* latency_us);
+/* Block until the request is done (then as pscl_server_poll), or for at
+ * most timeout_ms milliseconds (timeout_ms < 0: no limit), returning
+ * PSCL_E_TIMEOUT if it is not done by then (the ticket stays valid). */
+pscl_status pscl_server_wait(pscl_server* server, uint64_t ticket, double timeout_ms,
+                             double* latency_us);
 
 /* Requests, frames and launches completed, and the 50th / 99th percentile
  * latencies (microseconds) of those requests; reset != 0 clears them. */
@@ -344,14 +368,18 @@ pscl_status pscl_server_stats(pscl_server* server, int64_t* requests, int64_t* f
 /*
  * Replay a request trace: job i arrives arrival_us[i] microseconds after
  * the start (non-decreasing; the host clock is busy-waited).  Through
- * `server`, or, when server is NULL, as the plain baseline of one
- * pscl_decode per request with plans[job.plan], issued in arrival order on
- * `stream`.  Blocks until every request is done and writes each request's
- * latency (from its scheduled arrival, so queueing counts) and the elapsed
- * time from the start to the last completion.
+ * `server` (plans, n_plans and streams unused), or, when server is NULL, as
+ * the plain baseline of one pscl_decode per request, issued in arrival order
+ * round-robin on `streams` (1..8) streams of the replay's own: request i
+ * runs on stream i % streams with plan plans[(i % streams) * n_plans +
+ * job.plan], so `plans` holds `streams` sets of n_plans plans (one set per
+ * stream: calls on one plan must not overlap).  The jobs' inputs must be
+ * ready before the call.  Blocks until every request is done and writes
+ * each request's latency (from its scheduled arrival, so queueing counts)
+ * and the elapsed time from the start to the last completion.
  */
 pscl_status pscl_replay(pscl_server* server, const pscl_plan* const* plans, int n_plans,
-                        const pscl_job* jobs, const double* arrival_us, int n, void* stream,
+                        int streams, const pscl_job* jobs, const double* arrival_us, int n,
                         double* latency_us, double* elapsed_us);
 
 /*

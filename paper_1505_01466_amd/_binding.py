@@ -29,6 +29,7 @@ _STATUS = {
     4: "HIP runtime error",
     5: "no gfx950 device",
     6: "busy",
+    7: "timed out",
 }
 
 
@@ -58,7 +59,7 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("plans", ctypes.POINTER(ctypes.c_void_p)), ("n_plans", ctypes.c_int),
                 ("streams", ctypes.c_int), ("max_requests", ctypes.c_int),
                 ("max_pending_frames", ctypes.c_int64), ("max_batch_frames", ctypes.c_int64),
-                ("max_batch_requests", ctypes.c_int)]
+                ("max_batch_requests", ctypes.c_int), ("max_footprint_bytes", ctypes.c_int64)]
 
 
 def _load():
@@ -83,6 +84,8 @@ def _load():
     lib.pscl_plan_create.restype = c_int
     lib.pscl_plan_destroy.argtypes = [vp]
     lib.pscl_plan_destroy.restype = None
+    lib.pscl_plan_footprint.argtypes = [vp, ctypes.POINTER(c_i64)]
+    lib.pscl_plan_footprint.restype = c_int
     lib.pscl_plan_reserve.argtypes = [vp]
     lib.pscl_plan_reserve.restype = c_int
     lib.pscl_decode.argtypes = [vp, vp, c_i64, vp, vp, vp, vp]
@@ -114,18 +117,18 @@ def _load():
     lib.pscl_server_create.restype = c_int
     lib.pscl_server_destroy.argtypes = [vp]
     lib.pscl_server_destroy.restype = None
-    lib.pscl_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(c_u64)]
+    lib.pscl_server_submit.argtypes = [vp, ctypes.POINTER(Job), vp, ctypes.POINTER(c_u64)]
     lib.pscl_server_submit.restype = c_int
     dp = ctypes.POINTER(ctypes.c_double)
     lib.pscl_server_poll.argtypes = [vp, c_u64, ip, dp]
     lib.pscl_server_poll.restype = c_int
-    lib.pscl_server_wait.argtypes = [vp, c_u64, dp]
+    lib.pscl_server_wait.argtypes = [vp, c_u64, ctypes.c_double, dp]
     lib.pscl_server_wait.restype = c_int
     i64p = ctypes.POINTER(c_i64)
     lib.pscl_server_stats.argtypes = [vp, i64p, i64p, i64p, dp, dp, c_int]
     lib.pscl_server_stats.restype = c_int
-    lib.pscl_replay.argtypes = [vp, ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), dp, c_int, vp,
-                                dp, dp]
+    lib.pscl_replay.argtypes = [vp, ctypes.POINTER(vp), c_int, c_int, ctypes.POINTER(Job), dp,
+                                c_int, dp, dp]
     lib.pscl_replay.restype = c_int
     lib.pscl_adaptive_create.argtypes = [vp, vp, c_i64, ctypes.POINTER(vp)]
     lib.pscl_adaptive_create.restype = c_int
@@ -209,6 +212,12 @@ class Plan:
         return {"frames_per_wg": fw.value, "threads": nt.value, "workgroups": wg.value,
                 "lds_bytes": lds.value, "workspace_bytes": ws.value,
                 "first_global_stage": glob.value}
+
+    def footprint(self) -> int:
+        """Device bytes per frame in flight (pscl_plan_footprint)."""
+        b = ctypes.c_int64(0)
+        _check(lib.pscl_plan_footprint(self._h, ctypes.byref(b)), "pscl_plan_footprint")
+        return b.value
 
     def reserve(self):
         """Allocate the plan's workspace now (pscl_plan_reserve)."""
@@ -364,11 +373,11 @@ class Server:
 
     def __init__(self, plans, streams: int = 2, max_requests: int = 0,
                  max_pending_frames: int = 0, max_batch_frames: int = 0,
-                 max_batch_requests: int = 0):
+                 max_batch_requests: int = 0, max_footprint_bytes: int = 0):
         self.plans = list(plans)
         self._hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         cfg = ServerCfg(self._hs, len(self.plans), streams, max_requests, max_pending_frames,
-                        max_batch_frames, max_batch_requests)
+                        max_batch_frames, max_batch_requests, max_footprint_bytes)
         h = ctypes.c_void_p(None)
         _check(lib.pscl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pscl_server_create")
         self._h = h
@@ -376,11 +385,13 @@ class Server:
 
     def submit(self, plan_index: int, llr):
         """Queue F frames (llr F x N device tensor) of plans[plan_index];
-        returns (ticket, (u_hat, crc_ok, pm)).  Raises PsclError (status 6)
-        when the server is full."""
+        returns (ticket, (u_hat, crc_ok, pm)).  The request is decoded after
+        the work already issued on the current stream (which may still be
+        producing llr).  Raises PsclError (status 6) when the server is full."""
         arr, outs = _jobs(self.plans, [(plan_index, llr)])
         t = ctypes.c_uint64(0)
-        _check(lib.pscl_server_submit(self._h, arr, ctypes.byref(t)), "pscl_server_submit")
+        _check(lib.pscl_server_submit(self._h, arr, _stream_handle(llr.device), ctypes.byref(t)),
+               "pscl_server_submit")
         self._live[t.value] = (llr, outs[0])
         return t.value, outs[0]
 
@@ -395,9 +406,12 @@ class Server:
             return True, lat.value
         return False, None
 
-    def wait(self, ticket: int) -> float:
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> float:
+        """Latency in microseconds; raises PsclError (status 7) when the
+        request is not done within timeout_ms (negative: no limit)."""
         lat = ctypes.c_double(0.0)
-        _check(lib.pscl_server_wait(self._h, ticket, ctypes.byref(lat)), "pscl_server_wait")
+        _check(lib.pscl_server_wait(self._h, ticket, float(timeout_ms), ctypes.byref(lat)),
+               "pscl_server_wait")
         self._live.pop(ticket, None)
         return lat.value
 
@@ -423,23 +437,28 @@ class Server:
             pass
 
 
-def replay(plans, work, arrival_us, server=None):
+def replay(plans, work, arrival_us, server=None, streams: int = 1):
     """pscl_replay: request i = work[i] = (plan index, llr tensor) arrives
-    arrival_us[i] microseconds after the start; through `server`, or as one
-    pscl_decode per request when server is None.  Returns (outputs,
-    latencies in microseconds as a numpy array, elapsed microseconds)."""
+    arrival_us[i] microseconds after the start; through `server`, or, when
+    server is None, as one pscl_decode per request round-robin on `streams`
+    streams, plans then holding `streams` sets of the codes' plans
+    (len(plans) = streams * codes; a plan index in work names a code).
+    Returns (outputs, latencies in microseconds as a numpy array, elapsed
+    microseconds)."""
     plans = list(plans)
+    if server is None and len(plans) % streams:
+        raise ValueError("plans must hold one set of plans per stream")
+    n_codes = len(plans) if server is not None else len(plans) // streams
     hs = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
-    arr, outs = _jobs(plans, work)
+    arr, outs = _jobs(plans[:n_codes], work)
     arrivals = np.ascontiguousarray(np.asarray(arrival_us, dtype=np.float64))
     if arrivals.shape != (len(work),):
         raise ValueError("one arrival time per request")
     lat = np.zeros(len(work), dtype=np.float64)
     el = ctypes.c_double(0.0)
     dp = ctypes.POINTER(ctypes.c_double)
-    _check(lib.pscl_replay(server._h if server is not None else None, hs, len(plans), arr,
-                           arrivals.ctypes.data_as(dp), len(work),
-                           _stream_handle(plans[0].device), lat.ctypes.data_as(dp),
+    _check(lib.pscl_replay(server._h if server is not None else None, hs, n_codes, streams, arr,
+                           arrivals.ctypes.data_as(dp), len(work), lat.ctypes.data_as(dp),
                            ctypes.byref(el)), "pscl_replay")
     return outs, lat, el.value
 

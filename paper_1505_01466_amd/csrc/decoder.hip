@@ -2030,11 +2030,11 @@ struct pscl_plan {
     // pscl_plan_reserve), so that plans used only inside groups and
     // servers never hold one
     mutable uint8_t* d_ws = nullptr;
+    mutable int ws_grid = 0;  // workgroups the allocated workspace serves
     mutable std::mutex ws_mu;
     unsigned long long* d_counter = nullptr;  // frames handed out
     mutable KArgs args{};
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
-    int64_t ws_bytes = 0;
     const void* kernel = nullptr;
     std::vector<uint8_t> frozen;
 };
@@ -2362,19 +2362,38 @@ static void default_launch(int dtype, int L, int& threads, int& budget, int& wg_
     if (const char* e = getenv("PSCL_MAX_WG_PER_CU")) wg_cap = atoi(e);
 }
 
-// The plan's own workspace (full grid), allocated on first use.
-static pscl_status ensure_workspace(const pscl_plan* p) {
-    if (p->ws_bytes <= 0) return PSCL_OK;
+// The plan's own workspace, for at least `grid` workgroups: allocated on
+// first use, enlarged (to the next power of two workgroups, at most the full
+// grid) when a call needs more, so that plans used only for small calls hold
+// little memory.  Calls on one plan are ordered, so the old workspace is
+// idle once the device has finished the previous calls.
+static pscl_status ensure_workspace(const pscl_plan* p, int grid) {
+    if (p->args.ws_frame <= 0) return PSCL_OK;
     std::lock_guard<std::mutex> lk(p->ws_mu);
-    if (p->d_ws) return PSCL_OK;
+    if (p->d_ws && p->ws_grid >= grid) return PSCL_OK;
+    int want = 1;
+    while (want < grid) want <<= 1;
+    want = std::min(want, p->grid_max);
+    want = std::max(want, grid);
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess) return PSCL_E_HIP;
     if (cur != p->device && hipSetDevice(p->device) != hipSuccess) return PSCL_E_HIP;
+    pscl_status st = PSCL_OK;
+    if (p->d_ws) {
+        st = hip_status(hipDeviceSynchronize());
+        if (st == PSCL_OK) st = hip_status(hipFree(p->d_ws));
+        if (st == PSCL_OK) {
+            p->d_ws = nullptr;
+            p->ws_grid = 0;
+            p->args.ws = nullptr;
+        }
+    }
     uint8_t* ws = nullptr;
-    const pscl_status st = hip_status(hipMalloc((void**)&ws, (size_t)p->ws_bytes));
+    if (st == PSCL_OK) st = hip_status(hipMalloc((void**)&ws, (size_t)(p->args.ws_frame * want)));
     if (cur != p->device) (void)hipSetDevice(cur);
     if (st != PSCL_OK) return st;
     p->d_ws = ws;
+    p->ws_grid = want;
     p->args.ws = ws;
     return PSCL_OK;
 }
@@ -2415,6 +2434,8 @@ const char* pscl_status_str(pscl_status s) {
             return "no gfx950 device";
         case PSCL_E_BUSY:
             return "busy: the server holds as many requests as it admits";
+        case PSCL_E_TIMEOUT:
+            return "timed out";
     }
     return "unknown status";
 }
@@ -2541,7 +2562,6 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (e != hipSuccess || occ < 1) occ = 1;
     if (wg_cap > 0 && occ > wg_cap) occ = wg_cap;
     p->grid_max = occ * prop.multiProcessorCount;
-    p->ws_bytes = wsf * (int64_t)p->grid_max;
 
     std::vector<OpRec> ops = make_records(p, lay, k_glob);
     std::vector<uint64_t> syn(N, 0);
@@ -2590,14 +2610,21 @@ pscl_status pscl_plan_info(const pscl_plan* p, int* frames_per_wg, int* threads,
     if (threads) *threads = p->NT;
     if (workgroups) *workgroups = p->grid_max;
     if (lds_bytes) *lds_bytes = p->lds_bytes;
-    if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+    if (workspace_bytes) *workspace_bytes = p->args.ws_frame * (int64_t)p->grid_max;
     if (first_global_stage) *first_global_stage = p->k_glob;
+    return PSCL_OK;
+}
+
+pscl_status pscl_plan_footprint(const pscl_plan* p, int64_t* bytes_per_frame) {
+    if (!p || !bytes_per_frame) return PSCL_E_INVALID;
+    *bytes_per_frame = p->args.ws_frame + p->lds_bytes + (int64_t)p->N * elem_size(p->dtype) +
+                       p->K + 1 + 4;
     return PSCL_OK;
 }
 
 pscl_status pscl_plan_reserve(const pscl_plan* p) {
     if (!p) return PSCL_E_INVALID;
-    return ensure_workspace(p);
+    return ensure_workspace(p, p->grid_max);
 }
 
 pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t* u_hat,
@@ -2608,11 +2635,11 @@ pscl_status pscl_decode(const pscl_plan* p, const void* llr, int64_t F, uint8_t*
     if (((uintptr_t)llr & 15u) != 0) return PSCL_E_INVALID;  // 16-byte vector loads
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return PSCL_E_HIP;
-    if (!p->d_ws) {
-        const pscl_status st = ensure_workspace(p);
+    const int grid = (int)std::min<int64_t>(F, p->grid_max);
+    if (p->ws_grid < grid) {
+        const pscl_status st = ensure_workspace(p, grid);
         if (st != PSCL_OK) return st;
     }
-    const int grid = (int)std::min<int64_t>(F, p->grid_max);
     hipStream_t s = (hipStream_t)stream;
     // the frame counter starts at zero (a one-thread kernel, so that the
     // call can be captured in a graph)
@@ -2972,8 +2999,8 @@ pscl_status pscl_adaptive_create(const pscl_plan* fast, const pscl_plan* list, i
                                           : gathered_kernel_for<false>(list->dtype);
     pscl_status st = hip_status(
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, list->lds_bytes));
-    if (st == PSCL_OK) st = ensure_workspace(fast);
-    if (st == PSCL_OK) st = ensure_workspace(list);
+    if (st == PSCL_OK) st = ensure_workspace(fast, fast->grid_max);
+    if (st == PSCL_OK) st = ensure_workspace(list, list->grid_max);
     if (st != PSCL_OK) return st;
     pscl_adaptive* ad = new pscl_adaptive();
     ad->fast = fast;

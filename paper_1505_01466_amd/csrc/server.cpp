@@ -32,8 +32,10 @@ double now_us() {
 struct Req {
     pscl_job job;
     uint64_t ticket;
-    double t_arrive;  // latency reference
-    double* sink;     // if set, the latency goes here and the ticket is not kept
+    double t_arrive;     // latency reference
+    double* sink;        // if set, the latency goes here and the ticket is not kept
+    hipEvent_t ready;    // recorded on the submitter's stream (NULL: inputs resident)
+    int64_t footprint;   // device bytes charged to the admission budget
 };
 
 double percentile(std::vector<double> v, double q) {
@@ -55,12 +57,16 @@ struct pscl_server {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> ev;
     std::vector<std::vector<Req>> inflight;
+    std::vector<int64_t> frame_bytes;  // pscl_plan_footprint of each plan
+    int64_t max_footprint = 0;         // 0 = no limit
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Req> pending;
     int64_t pending_frames = 0;
-    int64_t held = 0;  // pending + in flight
+    int64_t held = 0;            // pending + in flight
+    int64_t held_footprint = 0;  // their device bytes
+    std::vector<hipEvent_t> free_events;  // readiness events to reuse
     std::unordered_map<uint64_t, double> done;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -71,7 +77,8 @@ struct pscl_server {
     std::thread th;
 
     void run();
-    pscl_status submit(const pscl_job& job, double t_arrive, double* sink, uint64_t* ticket);
+    pscl_status submit(const pscl_job& job, hipStream_t ready_on, bool order, double t_arrive,
+                       double* sink, uint64_t* ticket);
 };
 
 void pscl_server::run() {
@@ -95,6 +102,8 @@ void pscl_server::run() {
                 n_req += 1;
                 n_frames += r.job.F;
                 held -= 1;
+                held_footprint -= r.footprint;
+                if (r.ready) free_events.push_back(r.ready);
             }
             inflight[s].clear();
             progress = true;
@@ -119,8 +128,15 @@ void pscl_server::run() {
             }
             if (batch.empty()) continue;
             jobs.clear();
-            for (const Req& r : batch) jobs.push_back(r.job);
-            pscl_status st = pscl_group_decode(groups[s], jobs.data(), (int)jobs.size(), streams[s]);
+            pscl_status st = PSCL_OK;
+            for (const Req& r : batch) {
+                jobs.push_back(r.job);
+                // the launch runs after the work that produced the inputs
+                if (r.ready && hipStreamWaitEvent(streams[s], r.ready, 0) != hipSuccess)
+                    st = PSCL_E_HIP;
+            }
+            if (st == PSCL_OK)
+                st = pscl_group_decode(groups[s], jobs.data(), (int)jobs.size(), streams[s]);
             if (st == PSCL_OK && hipEventRecord(ev[s], streams[s]) != hipSuccess) st = PSCL_E_HIP;
             if (st != PSCL_OK) {
                 // the requests complete as failed; later calls report it
@@ -149,16 +165,45 @@ void pscl_server::run() {
     }
 }
 
-pscl_status pscl_server::submit(const pscl_job& job, double t_arrive, double* sink,
-                                 uint64_t* ticket) {
+pscl_status pscl_server::submit(const pscl_job& job, hipStream_t ready_on, bool order,
+                                 double t_arrive, double* sink, uint64_t* ticket) {
     if (job.plan < 0 || job.plan >= (int)plans.size() || job.F < 0) return PSCL_E_INVALID;
     if (job.F > 0 && (!job.llr || !job.u_hat || ((uintptr_t)job.llr & 15u) != 0))
         return PSCL_E_INVALID;
     if (max_pending_frames > 0 && job.F > max_pending_frames) return PSCL_E_INVALID;  // never fits
+    const int64_t fp = job.F * frame_bytes[job.plan];
+    if (max_footprint > 0 && fp > max_footprint) return PSCL_E_INVALID;  // never fits
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (error != PSCL_OK) return error;
+        if (held >= max_requests) return PSCL_E_BUSY;
+        if (max_pending_frames > 0 && pending_frames + job.F > max_pending_frames)
+            return PSCL_E_BUSY;
+        if (max_footprint > 0 && held_footprint + fp > max_footprint) return PSCL_E_BUSY;
+        if (order && job.F > 0 && !free_events.empty()) {
+            ev = free_events.back();
+            free_events.pop_back();
+        }
+    }
+    if (order && job.F > 0) {
+        // readiness of the inputs: an event on the submitter's stream
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return PSCL_E_HIP;
+        if (hipEventRecord(ev, ready_on) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            free_events.push_back(ev);
+            return PSCL_E_HIP;
+        }
+    }
     std::lock_guard<std::mutex> lk(mu);
-    if (error != PSCL_OK) return error;
-    if (held >= max_requests) return PSCL_E_BUSY;
-    if (max_pending_frames > 0 && pending_frames + job.F > max_pending_frames) return PSCL_E_BUSY;
+    // admission is re-checked: another thread may have submitted meanwhile
+    if (held >= max_requests ||
+        (max_pending_frames > 0 && pending_frames + job.F > max_pending_frames) ||
+        (max_footprint > 0 && held_footprint + fp > max_footprint)) {
+        if (ev) free_events.push_back(ev);
+        return PSCL_E_BUSY;
+    }
     const uint64_t t = next_ticket++;
     if (ticket) *ticket = t;
     if (job.F == 0) {  // nothing to decode: done at once
@@ -167,9 +212,10 @@ pscl_status pscl_server::submit(const pscl_job& job, double t_arrive, double* si
         cv_done.notify_all();
         return PSCL_OK;
     }
-    pending.push_back(Req{job, t, t_arrive, sink});
+    pending.push_back(Req{job, t, t_arrive, sink, ev, fp});
     pending_frames += job.F;
     held += 1;
+    held_footprint += fp;
     cv_work.notify_one();
     return PSCL_OK;
 }
@@ -189,6 +235,7 @@ void pscl_server_destroy(pscl_server* sv) {
     for (pscl_group* g : sv->groups) pscl_group_destroy(g);
     for (hipEvent_t e : sv->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
     for (hipStream_t s : sv->streams)
         if (s) (void)hipStreamDestroy(s);
     delete sv;
@@ -197,7 +244,8 @@ void pscl_server_destroy(pscl_server* sv) {
 pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
     if (!cfg || !out || !cfg->plans || cfg->n_plans < 1) return PSCL_E_INVALID;
     if (cfg->streams < 0 || cfg->streams > 8 || cfg->max_requests < 0 ||
-        cfg->max_pending_frames < 0 || cfg->max_batch_frames < 0 || cfg->max_batch_requests < 0)
+        cfg->max_pending_frames < 0 || cfg->max_batch_frames < 0 || cfg->max_batch_requests < 0 ||
+        cfg->max_footprint_bytes < 0)
         return PSCL_E_INVALID;
     for (int i = 0; i < cfg->n_plans; ++i)
         if (!cfg->plans[i]) return PSCL_E_INVALID;
@@ -212,7 +260,13 @@ pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
     sv->max_batch_frames = cfg->max_batch_frames;
     sv->plans.assign(cfg->plans, cfg->plans + cfg->n_plans);
     sv->inflight.resize(sv->S);
+    sv->max_footprint = cfg->max_footprint_bytes;
     pscl_status st = PSCL_OK;
+    for (int i = 0; i < cfg->n_plans && st == PSCL_OK; ++i) {
+        int64_t b = 0;
+        st = pscl_plan_footprint(cfg->plans[i], &b);
+        sv->frame_bytes.push_back(b);
+    }
     for (int s = 0; s < sv->S && st == PSCL_OK; ++s) {
         pscl_group* g = nullptr;
         st = pscl_group_create(cfg->plans, cfg->n_plans, sv->max_batch_requests, 1, nullptr, &g);
@@ -235,9 +289,10 @@ pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
     return PSCL_OK;
 }
 
-pscl_status pscl_server_submit(pscl_server* sv, const pscl_job* job, uint64_t* ticket) {
+pscl_status pscl_server_submit(pscl_server* sv, const pscl_job* job, void* stream,
+                               uint64_t* ticket) {
     if (!sv || !job) return PSCL_E_INVALID;
-    return sv->submit(*job, now_us(), nullptr, ticket);
+    return sv->submit(*job, (hipStream_t)stream, true, now_us(), nullptr, ticket);
 }
 
 pscl_status pscl_server_poll(pscl_server* sv, uint64_t ticket, int* is_done, double* latency_us) {
@@ -255,11 +310,19 @@ pscl_status pscl_server_poll(pscl_server* sv, uint64_t ticket, int* is_done, dou
     return sv->error;
 }
 
-pscl_status pscl_server_wait(pscl_server* sv, uint64_t ticket, double* latency_us) {
+pscl_status pscl_server_wait(pscl_server* sv, uint64_t ticket, double timeout_ms,
+                             double* latency_us) {
     if (!sv) return PSCL_E_INVALID;
     std::unique_lock<std::mutex> lk(sv->mu);
     if (ticket == 0 || ticket >= sv->next_ticket) return PSCL_E_INVALID;
-    sv->cv_done.wait(lk, [&] { return sv->done.count(ticket) > 0 || sv->error != PSCL_OK; });
+    auto ready = [&] { return sv->done.count(ticket) > 0 || sv->error != PSCL_OK; };
+    if (timeout_ms < 0) {
+        sv->cv_done.wait(lk, ready);
+    } else {
+        const auto limit = std::chrono::steady_clock::now() +
+                           std::chrono::microseconds((int64_t)(timeout_ms * 1e3));
+        if (!sv->cv_done.wait_until(lk, limit, ready)) return PSCL_E_TIMEOUT;
+    }
     auto it = sv->done.find(ticket);
     if (it == sv->done.end()) return sv->error;
     if (latency_us) *latency_us = it->second;
@@ -283,24 +346,27 @@ pscl_status pscl_server_stats(pscl_server* sv, int64_t* requests, int64_t* frame
     return sv->error;
 }
 
-pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_plans,
-                        const pscl_job* jobs, const double* arrival_us, int n, void* stream,
+pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_plans, int streams,
+                        const pscl_job* jobs, const double* arrival_us, int n,
                         double* latency_us, double* elapsed_us) {
     if (n < 0 || (n > 0 && (!jobs || !arrival_us || !latency_us))) return PSCL_E_INVALID;
-    if (!sv && (!plans || n_plans < 1)) return PSCL_E_INVALID;
+    if (!sv && (!plans || n_plans < 1 || streams < 1 || streams > 8)) return PSCL_E_INVALID;
     for (int i = 0; i < n; ++i) {
         if (i > 0 && arrival_us[i] < arrival_us[i - 1]) return PSCL_E_INVALID;
-        if (!sv && (jobs[i].plan < 0 || jobs[i].plan >= n_plans || !plans[jobs[i].plan]))
-            return PSCL_E_INVALID;
+        if (!sv && (jobs[i].plan < 0 || jobs[i].plan >= n_plans)) return PSCL_E_INVALID;
     }
-    const double t0 = now_us();
+    if (!sv)
+        for (int i = 0; i < n_plans * streams; ++i)
+            if (!plans[i]) return PSCL_E_INVALID;
     if (sv) {
+        const double t0 = now_us();
         for (int i = 0; i < n; ++i) {
             const double ta = t0 + arrival_us[i];
             while (now_us() < ta) {
             }
             for (;;) {
-                const pscl_status st = sv->submit(jobs[i], ta, &latency_us[i], nullptr);
+                const pscl_status st =
+                    sv->submit(jobs[i], nullptr, false, ta, &latency_us[i], nullptr);
                 if (st == PSCL_OK) break;
                 if (st != PSCL_E_BUSY) return st;
                 std::this_thread::yield();
@@ -311,51 +377,72 @@ pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_pl
         if (elapsed_us) *elapsed_us = now_us() - t0;
         return sv->error;
     }
-    // baseline: one pscl_decode per request on one stream, in arrival
-    // order; completions (in order, one stream) observed by a poller
-    hipStream_t s = (hipStream_t)stream;
+    // baseline: one pscl_decode per request, issued in arrival order
+    // round-robin over `streams` streams, request i with plan set i % streams
+    // (so that no two streams share a plan's workspace); each stream
+    // completes in order, observed by a poller
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PSCL_E_NODEV;
-    const int RING = 1024;
-    std::vector<hipEvent_t> evs(RING, nullptr);
+    const int S = streams;
+    const int RING = 1024;  // events per stream
+    std::vector<hipStream_t> str(S, nullptr);
+    std::vector<hipEvent_t> evs((size_t)S * RING, nullptr);
     pscl_status st = PSCL_OK;
-    for (int i = 0; i < RING && st == PSCL_OK; ++i)
+    for (int s = 0; s < S && st == PSCL_OK; ++s)
+        if (hipStreamCreateWithFlags(&str[s], hipStreamNonBlocking) != hipSuccess) st = PSCL_E_HIP;
+    for (size_t i = 0; i < evs.size() && st == PSCL_OK; ++i)
         if (hipEventCreateWithFlags(&evs[i], hipEventDisableTiming) != hipSuccess) st = PSCL_E_HIP;
+    // per stream: requests issued and completed (request i is the
+    // (i / S)-th of stream i % S)
     std::mutex mu;
     std::condition_variable cv;
-    int issued = 0, completed = 0;
+    std::vector<int> issued(S, 0), completed(S, 0);
+    int n_issued = 0, n_completed = 0;
     bool failed = false;
     std::vector<double> t_arr(n > 0 ? n : 1);
     std::thread poller;
+    const double t0 = now_us();
     if (st == PSCL_OK) {
         poller = std::thread([&] {
             (void)hipSetDevice(dev);
             for (;;) {
-                int head;
                 {
                     std::unique_lock<std::mutex> lk(mu);
-                    cv.wait(lk, [&] { return completed < issued || failed || completed == n; });
-                    if (completed == n || (failed && completed == issued)) return;
-                    head = completed;
+                    cv.wait(lk, [&] { return n_completed < n_issued || failed || n_completed == n; });
+                    if (n_completed == n || (failed && n_completed == n_issued)) return;
                 }
-                hipError_t q;
-                while ((q = hipEventQuery(evs[head % RING])) == hipErrorNotReady) std::this_thread::yield();
-                const double t = now_us();
-                std::lock_guard<std::mutex> lk(mu);
-                latency_us[head] = t - t_arr[head];
-                if (q != hipSuccess) failed = true;
-                completed += 1;
-                cv.notify_all();
+                bool any = false;
+                for (int s = 0; s < S; ++s) {
+                    int head;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        if (completed[s] >= issued[s]) continue;
+                        head = completed[s];
+                    }
+                    const hipError_t q = hipEventQuery(evs[(size_t)s * RING + head % RING]);
+                    if (q == hipErrorNotReady) continue;
+                    const double t = now_us();
+                    std::lock_guard<std::mutex> lk(mu);
+                    const int req = head * S + s;
+                    latency_us[req] = t - t_arr[req];
+                    if (q != hipSuccess) failed = true;
+                    completed[s] += 1;
+                    n_completed += 1;
+                    any = true;
+                    cv.notify_all();
+                }
+                if (!any) std::this_thread::yield();
             }
         });
     }
     for (int i = 0; i < n && st == PSCL_OK; ++i) {
+        const int s = i % S;
         const double ta = t0 + arrival_us[i];
         while (now_us() < ta) {
         }
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] { return issued - completed < RING || failed; });
+            cv.wait(lk, [&] { return issued[s] - completed[s] < RING || failed; });
             if (failed) {
                 st = PSCL_E_HIP;
                 break;
@@ -363,13 +450,16 @@ pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_pl
         }
         const pscl_job& J = jobs[i];
         t_arr[i] = ta;
-        st = pscl_decode(plans[J.plan], J.llr, J.F, J.u_hat, J.crc_ok, J.pm, s);
-        if (st == PSCL_OK && hipEventRecord(evs[i % RING], s) != hipSuccess) st = PSCL_E_HIP;
+        st = pscl_decode(plans[s * n_plans + J.plan], J.llr, J.F, J.u_hat, J.crc_ok, J.pm, str[s]);
+        if (st == PSCL_OK &&
+            hipEventRecord(evs[(size_t)s * RING + issued[s] % RING], str[s]) != hipSuccess)
+            st = PSCL_E_HIP;
         std::lock_guard<std::mutex> lk(mu);
         if (st != PSCL_OK) {
             failed = true;
         } else {
-            issued += 1;
+            issued[s] += 1;
+            n_issued += 1;
         }
         cv.notify_all();
     }
@@ -382,8 +472,12 @@ pscl_status pscl_replay(pscl_server* sv, const pscl_plan* const* plans, int n_pl
         poller.join();
     }
     if (elapsed_us) *elapsed_us = now_us() - t0;
+    for (hipStream_t x : str)
+        if (x) (void)hipStreamSynchronize(x);
     for (hipEvent_t e : evs)
         if (e) (void)hipEventDestroy(e);
+    for (hipStream_t x : str)
+        if (x) (void)hipStreamDestroy(x);
     if (st == PSCL_OK && failed) st = PSCL_E_HIP;
     return st;
 }

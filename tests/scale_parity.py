@@ -38,6 +38,20 @@ def frames(point_idx: int, sub: int):
     return b.info, {"f32": b.llr, "i8": synth.quantize(b.llr_f32, "i8")}
 
 
+def write_frames(args) -> dict:
+    """Process-pool worker: writes sub-chunk `sub` of point POINTS[pi] as .npy
+    files (information bits, float32 and int8 LLRs) into directory d and
+    returns their paths."""
+    pi, sub, d = args
+    info, llr = frames(pi, sub)
+    out = {}
+    for name, arr in (("info", info), ("f32", llr["f32"]), ("i8", llr["i8"])):
+        path = os.path.join(d, f"p{pi}_s{sub}_{name}.npy")
+        np.save(path, arr)
+        out[name] = path
+    return out
+
+
 def records(u: np.ndarray, ok: np.ndarray, pm: np.ndarray, dtype: str) -> np.ndarray:
     """One row of bytes per frame: packed u_hat bits, the CRC flag and the
     metric's 32 bits (float32 or int32)."""

@@ -36,8 +36,9 @@ def test_every_declared_symbol_is_exported(pk):
 
 
 def test_status_strings_and_version(pk):
-    for s in range(7):
+    for s in range(8):
         assert pk.lib.pscl_status_str(s)
+    assert pk.lib.pscl_status_str(7) == b"timed out"
     assert pk.lib.pscl_version() >= 100
 
 
@@ -189,22 +190,27 @@ def test_server_and_replay_validate_arguments(pk):
     assert pk.lib.pscl_server_create(None, ctypes.byref(h)) == 1
     plans = (vp * 1)(None)
     for bad in (dict(n_plans=0), dict(n_plans=1), dict(n_plans=1, streams=9),
-                dict(n_plans=1, max_requests=-1)):
+                dict(n_plans=1, max_requests=-1), dict(n_plans=1, footprint=-1)):
         cfg = pk.ServerCfg(plans, bad.get("n_plans", 1), bad.get("streams", 0),
-                           bad.get("max_requests", 0), 0, 0, 0)
+                           bad.get("max_requests", 0), 0, 0, 0, bad.get("footprint", 0))
         assert pk.lib.pscl_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 1
     assert not h.value
     t = ctypes.c_uint64()
     d = ctypes.c_int()
-    assert pk.lib.pscl_server_submit(None, None, ctypes.byref(t)) == 1
+    assert pk.lib.pscl_server_submit(None, None, None, ctypes.byref(t)) == 1
     assert pk.lib.pscl_server_poll(None, 1, ctypes.byref(d), None) == 1
-    assert pk.lib.pscl_server_wait(None, 1, None) == 1
+    assert pk.lib.pscl_server_wait(None, 1, -1.0, None) == 1
+    assert pk.lib.pscl_server_wait(None, 1, 5.0, None) == 1
+    assert pk.lib.pscl_plan_footprint(None, None) == 1
     assert pk.lib.pscl_server_stats(None, None, None, None, None, None, 0) == 1
     pk.lib.pscl_server_destroy(None)
-    # replay: no plans for the baseline, negative count, missing arrays
-    assert pk.lib.pscl_replay(None, None, 0, None, None, 0, None, None, None) == 1
-    assert pk.lib.pscl_replay(None, plans, 1, None, None, -1, None, None, None) == 1
-    assert pk.lib.pscl_replay(None, plans, 1, None, None, 2, None, None, None) == 1
+    # replay: no plans for the baseline, stream count outside 1..8, negative
+    # count, missing arrays
+    assert pk.lib.pscl_replay(None, None, 0, 1, None, None, 0, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, 0, None, None, 0, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, 9, None, None, 0, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, 1, None, None, -1, None, None) == 1
+    assert pk.lib.pscl_replay(None, plans, 1, 1, None, None, 2, None, None) == 1
 
 
 def test_adaptive_validates_arguments(pk):

@@ -89,7 +89,13 @@ def test_replay_poisson_arrivals(env, through_server):
     rng = np.random.default_rng(3)
     arrivals = np.cumsum(rng.exponential(1e6 / 20000.0, n))  # 20k requests/s
     sv = pk.Server(plans, streams=3) if through_server else None
-    outs, lat, elapsed = pk.replay(plans, work, arrivals, server=sv)
+    if through_server:
+        outs, lat, elapsed = pk.replay(plans, work, arrivals, server=sv)
+    else:
+        # per-request launches on 3 streams, a set of plans per stream
+        sets = plans + [pk.Plan(c.N, c.K, c.frozen, c.poly, c.r, spec[5], "i8")
+                        for _ in range(2) for c, spec in zip(codes, CODES)]
+        outs, lat, elapsed = pk.replay(sets, work, arrivals, streams=3)
     torch.cuda.synchronize()
     _check(outs, ref)
     _say(f"replay server={through_server}: p50 {np.percentile(lat, 50):.0f} us, "
@@ -174,4 +180,85 @@ def test_server_other_dtypes(env, dtype):
     torch.cuda.synchronize()
     _check([o for _, o in tickets], ref)
     _say(f"server {dtype}: {sv.stats()}")
+    sv.close()
+
+
+def test_submit_orders_after_the_producer(env):
+    """Inputs still being written on the submitter's stream when submit() is
+    called (a long chain of products first, then the device frame
+    generator): the server decodes them only after that work."""
+    pk, torch, codes, plans = env
+    code = codes[3]
+    gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, "i8")
+    F = 512
+    llr = torch.zeros((F, code.N), dtype=torch.int8, device="cuda")
+    info = torch.zeros((F, code.K), dtype=torch.uint8, device="cuda")
+    x = torch.randn(2048, 2048, device="cuda")
+    sv = pk.Server(plans, streams=2)
+    torch.cuda.synchronize()
+    for _ in range(30):  # keeps the current stream busy for a while
+        x = torch.tanh(x @ x) * 0.5
+    gen.generate(F, 4.0, 99, llr=llr, info=info)
+    t, out = sv.submit(3, llr)
+    sv.wait(t)
+    torch.cuda.synchronize()
+    ref = _alone(torch, plans, [(3, llr)])
+    _check([out], ref)
+    assert int(llr.abs().sum().item()) > 0
+    sv.close()
+    gen.close()
+
+
+def test_footprint_admission(env):
+    """max_footprint_bytes: a request is charged F * pscl_plan_footprint
+    bytes until it completes; a second request that would exceed the budget
+    is refused (busy) until the first is done, and one that exceeds it alone
+    is invalid."""
+    pk, torch, codes, plans = env
+    fp = plans[3].footprint()
+    assert fp > code_bytes(codes[3])
+    sv = pk.Server(plans, streams=1, max_footprint_bytes=int(1.5 * 64 * fp))
+    a = synth.make_batch(codes[3], 64, 4.0, (55, 1), "i8")
+    b = synth.make_batch(codes[3], 64, 4.0, (55, 2), "i8")
+    la, lb = torch.from_numpy(a.llr).cuda(), torch.from_numpy(b.llr).cuda()
+    torch.cuda.synchronize()
+    ta, oa = sv.submit(3, la)
+    with pytest.raises(pk.PsclError) as e:
+        sv.submit(3, lb)
+    assert e.value.status == 6
+    sv.wait(ta)
+    tb, ob = sv.submit(3, lb)
+    sv.wait(tb)
+    with pytest.raises(pk.PsclError) as e:  # 100 frames never fit
+        sv.submit(3, torch.zeros((100, codes[3].N), dtype=torch.int8, device="cuda"))
+    assert e.value.status == 1
+    torch.cuda.synchronize()
+    _check([oa, ob], _alone(torch, plans, [(3, la), (3, lb)]))
+    sv.close()
+
+
+def code_bytes(code):
+    return code.N + code.K + 1 + 4
+
+
+def test_wait_with_time_limit(env):
+    """wait(timeout) returns 'timed out' while the request cannot have run
+    (its inputs' stream is busy with a long chain of products), and the
+    ticket stays valid for a later wait."""
+    pk, torch, codes, plans = env
+    b = synth.make_batch(codes[2], 256, 4.0, (56, 1), "i8")
+    llr = torch.from_numpy(b.llr).cuda()
+    x = torch.randn(4096, 4096, device="cuda")
+    sv = pk.Server(plans, streams=1)
+    torch.cuda.synchronize()
+    for _ in range(40):
+        x = torch.tanh(x @ x) * 0.5
+    t, out = sv.submit(2, llr)
+    with pytest.raises(pk.PsclError) as e:
+        sv.wait(t, timeout_ms=1.0)
+    assert e.value.status == 7
+    lat = sv.wait(t, timeout_ms=60000.0)
+    assert lat > 0
+    torch.cuda.synchronize()
+    _check([out], _alone(torch, plans, [(2, llr)]))
     sv.close()
