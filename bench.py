@@ -176,9 +176,9 @@ def wilson(k, n, z=1.959964):
 def c4_codes(synth):
     """The mixed code set: N in {256..4096}, rate in {1/3, 1/2, 0.84} with
     K = round(R N) and the CRC inside K (CRC-8 below K = 256, else CRC-32),
-    Bhattacharyya design 2.5 dB for R <= 1/2 and 4.0 dB for R = 0.84 (also
-    the operating Eb/N0: the decoder's work does not depend on it), L in
-    {2, 8, 32}: 45 codes."""
+    Bhattacharyya design 2.5 dB for R <= 1/2 and 4.0 dB for R = 0.84, L in
+    {2, 8, 32}: 45 codes, as (code, L, design Eb/N0).  Their operating
+    points (FER = 1e-3) are in c4_points.json."""
     out = []
     for N in (256, 512, 1024, 2048, 4096):
         for R in (1 / 3, 1 / 2, 0.84):
@@ -192,19 +192,51 @@ def c4_codes(synth):
     return out
 
 
-def mixed_leg(pk, torch, synth, frames_per_code=1456, reps=3):
-    """One mixed launch over all 45 codes vs one launch per code, int8."""
+def c4_operating_points():
+    """Eb/N0 per mixed-workload code at FER <= 1e-3 (c4_points.json, written
+    by c4_points.py), keyed by (N, K, L); None when the table is missing."""
+    path = os.path.join(ROOT, "c4_points.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    return {(r["N"], r["K"], r["L"]): r["ebn0_db"] for r in t["codes"]}
+
+
+def mixed_leg(pk, torch, synth, total_frames=2_000_000, reps=2, tune_frac=16, seed=0x43340001):
+    """One persistent launch over all 45 codes (autotuned with
+    pscl_autotune_group on a 1/tune_frac sample) vs one launch per code with
+    default plans, int8, about total_frames frames in equal shares, each
+    code's frames made on the device at its FER = 1e-3 operating point
+    (c4_points.json; the design Eb/N0 when the table is missing).  Both must
+    return identical bits; FER per launch kind."""
     codes = c4_codes(synth)
-    plans, work, bits = [], [], 0
+    points = c4_operating_points()
+    per = -(-total_frames // len(codes))
+    work, work_small, bits, infos, ebn0 = [], [], 0, [], []
+    plans = []
     for i, (code, L, d) in enumerate(codes):
+        e = points[(code.N, code.K, L)] if points else d
+        ebn0.append(e)
+        gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, "i8")
+        llr, info = gen.generate(per, e, seed + i)
+        gen.close()
         plans.append(pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8"))
-        b = synth.make_batch(code, frames_per_code, d, (4, i), "i8")
-        work.append((i, torch.from_numpy(b.llr).cuda()))
-        bits += frames_per_code * (code.K - code.r)
-    group = pk.Group(plans, max_jobs=len(work), max_inflight=1)
+        work.append((i, llr))
+        work_small.append((i, llr[: max(1, per // tune_frac)]))
+        infos.append(info)
+        bits += per * (code.K - code.r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cfgs, threads, tune_ms = pk.autotune_group(plans, work_small)
+    tune_s = time.perf_counter() - t0
+    tuned = [pk.Plan(c.N, c.K, c.frozen, c.poly, c.r, L, "i8", cfg=cfg)
+             for (c, L, _), cfg in zip(codes, cfgs)]
+    group = pk.Group(tuned, max_jobs=len(work), max_inflight=1, threads=threads)
+    default_group = pk.Group(plans, max_jobs=len(work), max_inflight=1)
 
     def timed(fn):
-        fn()
+        out = fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -212,17 +244,33 @@ def mixed_leg(pk, torch, synth, frames_per_code=1456, reps=3):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / reps, out
 
-    ms_mixed = timed(lambda: group.decode(work))
-    ms_per_code = timed(lambda: [plans[i].decode(llr) for i, llr in work])
+    ms_tuned, out_tuned = timed(lambda: group.decode(work))
+    ms_default, _ = timed(lambda: default_group.decode(work))
+    ms_per_code, out_code = timed(lambda: [plans[i].decode(llr) for i, llr in work])
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+               for a, b in zip(out_tuned, out_code))
+    errs = sum(int((o[0] != inf).any(dim=1).sum().item()) for o, inf in zip(out_tuned, infos))
     group.close()
-    return {"codes": len(codes), "frames": frames_per_code * len(codes), "dtype": "i8",
-            "mixed_launch": {"ms": round(ms_mixed, 3), "gbps": round(bits / ms_mixed / 1e6, 4)},
+    default_group.close()
+    for p in tuned + plans:
+        p.close()
+    nf = per * len(codes)
+    return {"codes": len(codes), "frames": nf, "dtype": "i8",
+            "operating_points": "c4_points.json (FER 1e-3)" if points else "design Eb/N0",
+            "ebn0_db_range": [min(ebn0), max(ebn0)],
+            "autotuned_launch": {"ms": round(ms_tuned, 3), "gbps": round(bits / ms_tuned / 1e6, 4),
+                                 "threads": threads, "cfg": cfgs[0],
+                                 "tuning_s": round(tune_s, 1),
+                                 "tuning_sample_frames": sum(int(x.shape[0]) for _, x in work_small)},
+            "default_mixed_launch": {"ms": round(ms_default, 3),
+                                     "gbps": round(bits / ms_default / 1e6, 4)},
             "per_code_launches": {"ms": round(ms_per_code, 3),
                                   "gbps": round(bits / ms_per_code / 1e6, 4)},
+            "identical_outputs": bool(same), "fer": errs / nf,
             "workload": "N in {256..4096} x R in {1/3,1/2,0.84} x L in {2,8,32}, CRC inside K, "
-                        "BPSK-AWGN at each code's design Eb/N0"}
+                        "device-made BPSK-AWGN frames at each code's FER=1e-3 Eb/N0"}
 
 
 def quantile_ci(x, q, z=1.959964):
@@ -575,6 +623,8 @@ def main():
     ap.add_argument("--single", action="store_true",
                     help="time only --dtype (no int8, mixed or serving legs)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch leg")
+    ap.add_argument("--mixed-frames", type=int, default=2_000_000,
+                    help="frames of the mixed-launch leg (equal shares of the 45 codes)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-decoding leg")
     ap.add_argument("--no-spc-plus", action="store_true", help="skip the SPC-4 vs SPC-4+ leg")
@@ -748,7 +798,7 @@ def main():
         adaptive = adaptive_leg(pk, torch, code, args.frames)
     if not args.single and not args.no_mixed:
         print("[bench] mixed launch vs per-code launches", file=sys.stderr, flush=True)
-        mixed = mixed_leg(pk, torch, synth)
+        mixed = mixed_leg(pk, torch, synth, total_frames=args.mixed_frames)
     if not args.single and not args.no_serving:
         print("[bench] serving replay", file=sys.stderr, flush=True)
         serving = serving_leg(pk, torch, synth, np, span_s=args.serving_span,

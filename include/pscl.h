@@ -148,6 +148,16 @@ typedef struct {
     int threads;
     int lds_budget;
     int max_wg_per_cu; /* resident workgroups per CU at most (0 = as many as fit) */
+    /* LLR stages below the root that are recomputed from the channel row
+     * where they are read instead of being stored, when they would live in
+     * the workspace and only F / G / Combine touch their levels: 1 = none,
+     * 2 = the stage of level n - 1, 3 = those of levels n - 1 and n - 2
+     * (0 = default: 2 for float32 and int16, 1 for int8). */
+    int recompute;
+    /* float32 with L <= 32 only: forking leaves of at most 2^fuse_log2
+     * values are scored, ranked and written in one wavefront (-1 = never,
+     * 1..5; 0 = default 5); ignored otherwise. */
+    int fuse_log2;
 } pscl_launch_cfg;
 
 /* pscl_plan_create with an explicit launch shape (cfg may be NULL).
@@ -158,12 +168,17 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
 
 /*
  * Autotuner: times pscl_decode of the caller's F frames (llr: device, F x N,
- * as for pscl_decode, F >= 1) under every distinct launch shape among
- * threads in {64, 128, 256} and LDS budgets from 8 to 48 KiB, on the given
- * stream, and writes the fastest shape to *best (and its time per call, in
- * milliseconds, to *best_ms when not NULL).  Allocates and frees plans and
- * output buffers while it runs, so it belongs to set-up, not to a decoding
- * loop.  Same argument rules and errors as pscl_plan_create.
+ * as for pscl_decode, F >= 1) on the given stream and writes the fastest
+ * launch configuration found to *best (and its time per call, in
+ * milliseconds, to *best_ms when not NULL).  The search runs coordinate by
+ * coordinate, each plan that differs from those already timed being timed
+ * once: waves per frame (threads 64, 128, 256) x LDS budget (8 to 48 KiB:
+ * which tree levels stay on chip); then the stages recomputed below the
+ * root (recompute 1..3); then, for float32 with L <= 32, the largest fused
+ * forking leaf (fuse_log2 -1, 3, 4, 5); then a residency cap (2, 4, 8
+ * workgroups per CU).  Allocates and frees plans and output buffers while
+ * it runs, so it belongs to set-up, not to a decoding loop.  Same argument
+ * rules and errors as pscl_plan_create.
  */
 pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc_poly,
                           int crc_len, int L, int dtype, int spc_max, int mode,
@@ -272,6 +287,25 @@ typedef struct pscl_group pscl_group;
  */
 pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int max_jobs,
                               int max_inflight, const pscl_launch_cfg* cfg, pscl_group** out);
+
+/*
+ * Autotuner of a mixed launch: times pscl_group_decode of the caller's jobs
+ * (job.plan indexes `plans`, whose codes define the trial plans; buffers as
+ * for pscl_group_decode) on the stream, with every plan rebuilt under one
+ * launch configuration at a time, searched coordinate by coordinate: group
+ * threads (64, 128, 256) x LDS budget per plan (8 to 32 KiB); then the
+ * stages recomputed below the root (recompute 1..3); then, for float32, the
+ * largest fused forking leaf (fuse_log2 -1, 4, 5).  Writes the fastest
+ * configuration for each plan to cfgs[0 .. n_plans) (pass each to
+ * pscl_plan_create_cfg), the group's threads to *threads (pass them to
+ * pscl_group_create) and the time per call in milliseconds to *best_ms
+ * when not NULL.  Allocates and frees plans and groups while it runs (set-up
+ * work).  PSCL_E_INVALID for missing arguments, plans of different dtypes
+ * or a job whose plan index is out of range.
+ */
+pscl_status pscl_autotune_group(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
+                                int n_jobs, void* stream, pscl_launch_cfg* cfgs, int* threads,
+                                float* best_ms);
 
 /* Release a group (NULL allowed) after its launches have finished. */
 void pscl_group_destroy(pscl_group* group);

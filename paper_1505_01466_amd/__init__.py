@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     Server,
     ServerCfg,
     autotune,
+    autotune_group,
     decode,
     decode_mixed,
     lib,

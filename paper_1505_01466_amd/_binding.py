@@ -43,7 +43,8 @@ class LaunchCfg(ctypes.Structure):
     """pscl_launch_cfg: threads per workgroup and LDS budget (0 = default)."""
 
     _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int),
-                ("max_wg_per_cu", ctypes.c_int)]
+                ("max_wg_per_cu", ctypes.c_int), ("recompute", ctypes.c_int),
+                ("fuse_log2", ctypes.c_int)]
 
 
 class Job(ctypes.Structure):
@@ -107,6 +108,10 @@ def _load():
     lib.pscl_group_create.argtypes = [ctypes.POINTER(vp), c_int, c_int, c_int,
                                       ctypes.POINTER(LaunchCfg), ctypes.POINTER(vp)]
     lib.pscl_group_create.restype = c_int
+    lib.pscl_autotune_group.argtypes = [ctypes.POINTER(vp), c_int, ctypes.POINTER(Job), c_int, vp,
+                                        ctypes.POINTER(LaunchCfg), ip,
+                                        ctypes.POINTER(ctypes.c_float)]
+    lib.pscl_autotune_group.restype = c_int
     lib.pscl_group_destroy.argtypes = [vp]
     lib.pscl_group_destroy.restype = None
     lib.pscl_group_decode.argtypes = [vp, ctypes.POINTER(Job), c_int, vp]
@@ -186,7 +191,8 @@ class Plan:
 
     def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int,
                  dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE,
-                 threads: int = 0, lds_budget: int = 0, max_wg_per_cu: int = 0):
+                 threads: int = 0, lds_budget: int = 0, max_wg_per_cu: int = 0,
+                 recompute: int = 0, fuse_log2: int = 0, cfg: dict | None = None):
         import torch
 
         if dtype not in DTYPES:
@@ -196,7 +202,13 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device())
         fz = _mask(frozen)
         h = ctypes.c_void_p(None)
-        cfg = LaunchCfg(threads, lds_budget, max_wg_per_cu)
+        if cfg is not None:  # a configuration as autotune() returns it
+            threads, lds_budget = cfg.get("threads", 0), cfg.get("lds_budget", 0)
+            max_wg_per_cu = cfg.get("max_wg_per_cu", 0)
+            recompute, fuse_log2 = cfg.get("recompute", 0), cfg.get("fuse_log2", 0)
+        self.cfg = {"threads": threads, "lds_budget": lds_budget, "max_wg_per_cu": max_wg_per_cu,
+                    "recompute": recompute, "fuse_log2": fuse_log2}
+        cfg = LaunchCfg(threads, lds_budget, max_wg_per_cu, recompute, fuse_log2)
         _check(lib.pscl_plan_create_cfg(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype],
                                         spc_max, mode, ctypes.byref(cfg), ctypes.byref(h)),
                "pscl_plan_create_cfg")
@@ -297,7 +309,8 @@ def autotune(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr,
                              llr.data_ptr(), llr.shape[0], _stream_handle(llr.device),
                              ctypes.byref(best), ctypes.byref(ms)), "pscl_autotune")
     return ({"threads": best.threads, "lds_budget": best.lds_budget,
-             "max_wg_per_cu": best.max_wg_per_cu}, ms.value)
+             "max_wg_per_cu": best.max_wg_per_cu, "recompute": best.recompute,
+             "fuse_log2": best.fuse_log2}, ms.value)
 
 
 def _jobs(plans, work):
@@ -320,6 +333,24 @@ def _jobs(plans, work):
         arr[i] = Job(pi, llr.data_ptr(), F, u.data_ptr(), ok.data_ptr(), pm.data_ptr())
         outs.append((u, ok, pm))
     return arr, outs
+
+
+def autotune_group(plans, work):
+    """pscl_autotune_group on work = [(plan index, llr tensor), ...]: returns
+    (one configuration dict per plan, group threads, milliseconds per
+    call).  Rebuild the plans with Plan(..., cfg=c) and the group with
+    Group(plans, threads=t)."""
+    plans = list(plans)
+    hs = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    arr, _ = _jobs(plans, work)
+    cfgs = (LaunchCfg * len(plans))()
+    t = ctypes.c_int(0)
+    ms = ctypes.c_float(0.0)
+    _check(lib.pscl_autotune_group(hs, len(plans), arr, len(work), _stream_handle(plans[0].device),
+                                   cfgs, ctypes.byref(t), ctypes.byref(ms)), "pscl_autotune_group")
+    out = [{"threads": c.threads, "lds_budget": c.lds_budget, "max_wg_per_cu": c.max_wg_per_cu,
+            "recompute": c.recompute, "fuse_log2": c.fuse_log2} for c in cfgs]
+    return out, t.value, ms.value
 
 
 class Group:

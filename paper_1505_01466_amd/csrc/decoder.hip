@@ -404,6 +404,8 @@ struct KArgs {
     int64_t ws_frame;  // workspace bytes per workgroup
     int n_ops, N, n, K, L, has_crc;
     int ptrA_off, ptrB_off, pm_off, root_off, root_sp;
+    int vt2_off;  // left partial sums of level n - 2 (stages n - 1, n - 2 recomputed)
+    int fuse_k;   // float32: forking leaves of at most 2^fuse_k values run fused (-1: none)
     int rs;  // bytes per path-table row (one byte per tree level, 4-aligned)
     // candidate scratch
     int spm_off, ckey_off, surv_off, sinfo_off;
@@ -421,6 +423,7 @@ struct Ctx {
     int N, n, L, tid, NT, lane;
     int ptrA_off, ptrB_off, pm_off, rs;
     int spm_off, ckey_off, surv_off, sinfo_off;
+    int vt2_off;
     int cur;  // which copy of the path tables is current
 
     // Path -> buffer tables, one 16-byte row per slot (entry k = tree level
@@ -550,6 +553,57 @@ DEV void pp_fg_virtual(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     if (q.g == 0) c.setA(k - 1, q.p);
 }
 
+// F / G two levels below the root (k = n - 2) reading the node's input
+// without either stage above it being stored: with the channel of 8M values
+// (M = node outputs), stage n - 1 is a1[i] = F(ch[i], ch[i + 4M]) in the
+// root's left half or G(ch[i], ch[i + 4M], b1[i]) in its right half (b1 =
+// the root-left partial sums, op.x), and the node's input is a2[j] =
+// F(a1[j], a1[j + 2M]) under a left level-(n-1) parent or G(a1[j],
+// a1[j + 2M], b2[j]) under a right one (b2 = that parent's left partial
+// sums, at the plan's vt2_off).  Flags: side bit = right half of the root,
+// candidate-count bit 0 = right child of its level-(n-1) parent.  Same
+// arithmetic, in the same order, as storing both stages.
+template <typename T, bool IS_G, int OSP>
+DEV void pp_fg_virtual2(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
+    using IO = VecIO<T>;
+    using CF = ChunkFG<T>;
+    constexpr int LOGV = IO::LOGV;
+    const int M = 1 << (k - 1);
+    const bool right1 = op_side(op) != 0;
+    const bool right2 = (op_cand(op) & 1) != 0;
+    const T* ch = c.chan;
+    T* out = c.template stage<OSP>(op.y, k - 1, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.template bw<OSP>(op.z, k - 1, c.srcB(k - 1, q.p));
+    const uint32_t* b1 = right1 ? c.template bw<SP_WS>(op.x, k + 1, c.srcB(k + 1, q.p)) : nullptr;
+    const uint32_t* b2 = right2 ? c.template bw<SP_WS>(c.vt2_off, k, c.srcB(k, q.p)) : nullptr;
+    const int nch = M >> LOGV;
+    auto bits = [&](const uint32_t* w, int e) { return w[e >> 5] >> (e & 31); };
+    auto ld = [&](int i) { return CF::clamp(*(const uint4*)(ch + i)); };
+    auto op1 = [&](const uint4& u, const uint4& v, int i) {
+        return right1 ? CF::g(u, v, bits(b1, i)) : CF::f(u, v);
+    };
+    auto op2 = [&](const uint4& u, const uint4& v, int j) {
+        return right2 ? CF::g(u, v, bits(b2, j)) : CF::f(u, v);
+    };
+    for (int ch0 = q.g; ch0 < nch; ch0 += q.G) {
+        const int e = ch0 << LOGV;
+        // stage n - 1 at e, e + 2M (for input e) and M + e, 3M + e (for
+        // input M + e), each from channel elements i and i + 4M
+        const uint4 c0 = ld(e), c1 = ld(e + 4 * M);
+        const uint4 c2 = ld(e + 2 * M), c3 = ld(e + 6 * M);
+        const uint4 c4 = ld(M + e), c5 = ld(5 * M + e);
+        const uint4 c6 = ld(3 * M + e), c7 = ld(7 * M + e);
+        const uint4 x = op2(op1(c0, c1, e), op1(c2, c3, e + 2 * M), e);
+        const uint4 y = op2(op1(c4, c5, M + e), op1(c6, c7, 3 * M + e), M + e);
+        uint4 r;
+        if constexpr (IS_G) r = CF::g(x, y, bits(bl, e));
+        else r = CF::f(x, y);
+        *(uint4*)(out + e) = r;
+    }
+    if (q.g == 0) c.setA(k - 1, q.p);
+}
+
 template <typename T, bool IS_G, int ISP, int OSP>
 DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     using IO = VecIO<T>;
@@ -561,7 +615,8 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     if (!q.valid) return;
     const int M = 1 << (k - 1);
     if constexpr (ISP == SP_VT) {
-        pp_fg_virtual<T, IS_G, OSP>(c, op, k, q);
+        if (op_cand(op) & 8) pp_fg_virtual2<T, IS_G, OSP>(c, op, k, q);
+        else pp_fg_virtual<T, IS_G, OSP>(c, op, k, q);
         return;
     }
     const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, q.p));
@@ -1766,6 +1821,7 @@ DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
     c.ckey_off = a.ckey_off;
     c.surv_off = a.surv_off;
     c.sinfo_off = a.sinfo_off;
+    c.vt2_off = a.vt2_off;
 }
 
 // Schedule records are read with scalar loads (sched points into a
@@ -1824,7 +1880,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                     // a short forking leaf: fused in one wavefront (measured
                     // faster for float32 only, whose workgroups span two
                     // wavefronts; its networks hold at most 32 paths)
-                    if (k <= 5) {
+                    if (k <= a.fuse_k) {
                         P = fork_small<T>(c, op, type, k, side, cc, P);
                         q = make_grp(c.tid, c.NT, P);
                         __syncthreads();
@@ -2035,6 +2091,8 @@ struct pscl_plan {
     unsigned long long* d_counter = nullptr;  // frames handed out
     mutable KArgs args{};
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
+    int recompute = 0;  // stages below the root recomputed at most (0..2)
+    int fuse_k = -1;    // float32 fused forks up to 2^fuse_k values (-1: none)
     const void* kernel = nullptr;
     std::vector<uint8_t> frozen;
 };
@@ -2195,11 +2253,11 @@ struct Layout {
     int64_t ws_frame;
 };
 
-bool virtual_top(const pscl_plan* p, int k_glob);
+int virtual_depth(const pscl_plan* p, int k_glob);
 
 int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     const int L = p->L, n = p->n, es = elem_size(p->dtype);
-    const bool vt = virtual_top(p, k_glob);
+    const int vd = virtual_depth(p, k_glob);
     int off = 0;
     int64_t woff = 0;
     auto place = [&](int bytes, bool lds) {
@@ -2213,8 +2271,8 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
         return v;
     };
     for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
-    for (int k = 0; k < n; ++k)  // the stage below the root is not stored when recomputed
-        lay.a_off[k] = (vt && k == n - 1) ? 0 : place(L * (1 << k) * es, k < k_glob);
+    for (int k = 0; k < n; ++k)  // the stages below the root are not stored when recomputed
+        lay.a_off[k] = (k >= n - vd) ? 0 : place(L * (1 << k) * es, k < k_glob);
     for (int k = 0; k <= n; ++k) {
         const int bytes = L * words_host(k) * 4;
         if (k < n) lay.bl_off[k] = place(bytes, k < k_glob);  // the root is never a left child
@@ -2240,56 +2298,74 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
     off = align16(off + 16 * L);
     a.root_off = lay.br_off[n];
     a.root_sp = n < k_glob ? SP_LDS : SP_WS;
+    a.vt2_off = n >= 2 ? lay.bl_off[n - 2] : 0;
     lay.ws_frame = woff;
     return off;
 }
 
 // Operation records: the schedule with every operand offset and space.
-// The stage below the root can be recomputed instead of stored when it
-// would live in the workspace and only F / G operations read it.  For int8
-// the recomputation (four clamped channel chunks per output chunk) costs
-// more than the traffic it saves (measured), so int8 keeps storing it.
-bool virtual_top(const pscl_plan* p, int k_glob) {
+// The stages below the root can be recomputed instead of stored when they
+// would live in the workspace and only F / G / Combine operations touch
+// their levels: the stage of level n - 1 (depth 1: the F / G at level n - 1
+// read four channel chunks per output chunk) or those of levels n - 1 and
+// n - 2 as well (depth 2: the F / G at level n - 2 read eight), at most the
+// plan's `recompute` levels.
+int virtual_depth(const pscl_plan* p, int k_glob) {
     const int n = p->n;
-    if (p->dtype == PSCL_I8) return false;
-    if (n < 3 || n - 1 < k_glob || p->sched.empty()) return false;
-    if (p->sched[0].type != OP_F || p->sched[0].k != n) return false;  // root is split
-    for (const SchedOp& s : p->sched)
-        if (s.k == n - 1 && s.type != OP_F && s.type != OP_G && s.type != OP_COMB) return false;
+    if (p->recompute <= 0) return 0;
+    if (n < 3 || n - 1 < k_glob || p->sched.empty()) return 0;
+    if (p->sched[0].type != OP_F || p->sched[0].k != n) return 0;  // root is split
+    auto only_fgc = [&](int lvl) {
+        for (const SchedOp& s : p->sched)
+            if (s.k == lvl && s.type != OP_F && s.type != OP_G && s.type != OP_COMB) return false;
+        return true;
+    };
     // the stage must be wide enough for whole vector chunks
-    return (1 << (n - 2)) >= 16;
+    const int V = 16 / elem_size(p->dtype);
+    if (!only_fgc(n - 1) || (1 << (n - 2)) < V) return 0;
+    if (p->recompute >= 2 && n - 2 >= k_glob && only_fgc(n - 2) && (1 << (n - 3)) >= V) return 2;
+    return 1;
 }
 
 std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glob) {
     const int n = p->n;
     auto lvl = [&](int k) { return k < k_glob ? SP_LDS : SP_WS; };
-    const bool vt = virtual_top(p, k_glob);
-    bool right_half = false;  // past the root's G
+    const int vd = virtual_depth(p, k_glob);
+    bool right1 = false;  // past the root's G
+    bool right2 = false;  // under the right child of a level-(n - 1) node
     std::vector<OpRec> out;
     for (const SchedOp& s : p->sched) {
         OpRec r{};
         const int k = s.k;
         int isp, osp;
-        if (vt && k == n && (s.type == OP_F || s.type == OP_G)) {
+        const bool fg = s.type == OP_F || s.type == OP_G;
+        if (vd >= 1 && k == n && fg) {
             // the root's F / G: recomputed where used
-            if (s.type == OP_G) right_half = true;
+            if (s.type == OP_G) right1 = true;
             r.meta = (uint16_t)OP_NOP;
             out.push_back(r);
             continue;
         }
-        if (vt && k == n - 1 && (s.type == OP_F || s.type == OP_G)) {
+        if (vd == 2 && k == n - 1 && fg) {
+            right2 = s.type == OP_G;
+            r.meta = (uint16_t)OP_NOP;
+            out.push_back(r);
+            continue;
+        }
+        if (fg && vd >= 1 && k == n - vd) {
             isp = SP_VT;
             osp = lvl(k - 1);
             r.x = (uint16_t)lay.bl_off[n - 1];  // the root's left-half partial sums
             r.y = (uint16_t)lay.a_off[k - 1];
             r.z = (uint16_t)lay.bl_off[k - 1];
+            const uint32_t cand = vd == 2 ? (8u | (right2 ? 1u : 0u)) : 0u;
             r.meta = (uint16_t)((uint32_t)s.type | ((uint32_t)k << 3) |
-                                ((uint32_t)(right_half ? 1 : 0) << 7) | ((uint32_t)isp << 12) |
-                                ((uint32_t)osp << 14));
+                                ((uint32_t)(right1 ? 1 : 0) << 7) | (cand << 8) |
+                                ((uint32_t)isp << 12) | ((uint32_t)osp << 14));
             out.push_back(r);
             continue;
         }
-        if (s.type == OP_F || s.type == OP_G) {
+        if (fg) {
             isp = k == n ? SP_CH : lvl(k);
             osp = lvl(k - 1);
             r.x = (uint16_t)(k < n ? lay.a_off[k] : 0);
@@ -2341,6 +2417,18 @@ static void drop_cached_groups(const pscl_plan* p) {
         }
     }
     for (pscl_group* g : dead) pscl_group_destroy(g);
+}
+
+// Measured defaults at (2048,1723) L = 32: recomputing the stage below the
+// root pays for float32 and int16 (it saves its write and re-read), not for
+// int8 (four clamped channel chunks per output chunk cost more than the
+// traffic saved), and recomputing two levels costs more than it saves in
+// every dtype; fusing forking leaves of up to 32 values in one wavefront
+// pays for float32 (two wavefronts per frame) and not for the integer
+// dtypes (one), whose kernels do not carry the fused form.
+static void default_layout(int dtype, int L, int& recompute, int& fuse_k) {
+    recompute = dtype == PSCL_I8 ? 0 : 1;
+    fuse_k = (dtype == PSCL_F32 && L <= 32) ? 5 : -1;
 }
 
 static void default_launch(int dtype, int L, int& threads, int& budget, int& wg_cap) {
@@ -2494,6 +2582,18 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (cfg && cfg->max_wg_per_cu) wg_cap = cfg->max_wg_per_cu;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
     if (budget < 0 || wg_cap < 0) return PSCL_E_INVALID;
+    int recompute = 0, fuse_k = -1;
+    default_layout(dtype, L, recompute, fuse_k);
+    if (cfg && cfg->recompute) {
+        if (cfg->recompute < 1 || cfg->recompute > 3) return PSCL_E_INVALID;
+        recompute = cfg->recompute - 1;
+    }
+    if (cfg && cfg->fuse_log2) {
+        if (cfg->fuse_log2 < -1 || cfg->fuse_log2 > 5) return PSCL_E_INVALID;
+        // only the float32 kernels for lists of at most 32 paths carry the
+        // fused form
+        fuse_k = (dtype == PSCL_F32 && L <= 32) ? cfg->fuse_log2 : -1;
+    }
     if (NT < L && L > 64) return PSCL_E_UNSUPPORTED;
     int kk = 0;
     for (int i = 0; i < N; ++i) kk += frozen_mask[i] ? 0 : 1;
@@ -2516,6 +2616,8 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     p->poly = crc_poly;
     p->device = dev;
     p->frozen.assign(frozen_mask, frozen_mask + N);
+    p->recompute = recompute;
+    p->fuse_k = fuse_k;
     while ((1 << p->n) < N) p->n++;
     if (!build_schedule(N, frozen_mask, L, spc_max, mode, p->sched)) {
         delete p;
@@ -2598,6 +2700,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     a.L = L;
     p->k_glob = k_glob;
     a.has_crc = crc_len > 0 ? 1 : 0;
+    a.fuse_k = fuse_k;
     p->args = a;
     *out = p;
     return PSCL_OK;
@@ -2743,40 +2846,69 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     if (st == PSCL_OK) st = hip_status(hipEventCreate(&e0));
     if (st == PSCL_OK) st = hip_status(hipEventCreate(&e1));
     float best_t = -1.f;
-    std::vector<std::tuple<int, int, int>> seen;  // threads, LDS bytes, workgroups
+    pscl_launch_cfg cur{};
+    // plans already timed: (threads, LDS bytes, workgroups, recompute, fuse)
+    std::vector<std::tuple<int, int, int, int, int>> seen;
+    // times one shape (skipped when it builds a plan already timed);
+    // remembers the fastest
+    auto trial = [&](const pscl_launch_cfg& cfg) {
+        if (st != PSCL_OK) return;
+        pscl_plan* p = nullptr;
+        const pscl_status cs = pscl_plan_create_cfg(N, K, frozen_mask, crc_poly, crc_len, L, dtype,
+                                                    spc_max, mode, &cfg, &p);
+        if (cs != PSCL_OK) {
+            if (cs != PSCL_E_UNSUPPORTED && cs != PSCL_E_NOMEM) st = cs;
+            return;
+        }
+        const std::tuple<int, int, int, int, int> key{p->NT, p->lds_bytes, p->grid_max,
+                                                      virtual_depth(p, p->k_glob), p->fuse_k};
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
+            pscl_plan_destroy(p);
+            return;
+        }
+        seen.push_back(key);
+        st = pscl_decode(p, llr, F, u, ok, pm, stream);  // warm-up (allocates the workspace)
+        if (st == PSCL_OK) st = hip_status(hipEventRecord(e0, s));
+        for (int r = 0; r < 2 && st == PSCL_OK; ++r) st = pscl_decode(p, llr, F, u, ok, pm, stream);
+        if (st == PSCL_OK) st = hip_status(hipEventRecord(e1, s));
+        if (st == PSCL_OK) st = hip_status(hipEventSynchronize(e1));
+        float ms = 0.f;
+        if (st == PSCL_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+        pscl_plan_destroy(p);
+        ms *= 0.5f;
+        if (st == PSCL_OK && (best_t < 0.f || ms < best_t)) {
+            best_t = ms;
+            cur = cfg;
+        }
+    };
+    // 1. waves per frame and LDS budget (which tree levels stay on chip)
     const int threads[] = {64, 128, 256};
     const int budgets[] = {8192, 10240, 12288, 16384, 20480, 24576, 32768, 49152};
-    for (int t : threads) {
-        for (int b : budgets) {
-            if (st != PSCL_OK) break;
-            pscl_launch_cfg cfg{t, b, 0};
-            pscl_plan* p = nullptr;
-            pscl_status cs = pscl_plan_create_cfg(N, K, frozen_mask, crc_poly, crc_len, L, dtype,
-                                                  spc_max, mode, &cfg, &p);
-            if (cs != PSCL_OK) {
-                if (cs == PSCL_E_UNSUPPORTED || cs == PSCL_E_NOMEM) continue;
-                st = cs;
-                break;
-            }
-            const std::tuple<int, int, int> key{p->NT, p->lds_bytes, p->grid_max};
-            if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
-                pscl_plan_destroy(p);
-                continue;
-            }
-            seen.push_back(key);
-            st = pscl_decode(p, llr, F, u, ok, pm, stream);  // warm-up
-            if (st == PSCL_OK) st = hip_status(hipEventRecord(e0, s));
-            for (int r = 0; r < 2 && st == PSCL_OK; ++r) st = pscl_decode(p, llr, F, u, ok, pm, stream);
-            if (st == PSCL_OK) st = hip_status(hipEventRecord(e1, s));
-            if (st == PSCL_OK) st = hip_status(hipEventSynchronize(e1));
-            float ms = 0.f;
-            if (st == PSCL_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1));
-            pscl_plan_destroy(p);
-            ms *= 0.5f;
-            if (st == PSCL_OK && (best_t < 0.f || ms < best_t)) {
-                best_t = ms;
-                *best = cfg;
-            }
+    for (int t : threads)
+        for (int b : budgets) trial(pscl_launch_cfg{t, b, 0, 0, 0});
+    // 2. stages recomputed below the root, at the best shape
+    const pscl_launch_cfg shape = cur;
+    for (int rc = 1; rc <= 3; ++rc) {
+        pscl_launch_cfg c = shape;
+        c.recompute = rc;
+        trial(c);
+    }
+    // 3. fused short forks (float32, L <= 32)
+    if (dtype == PSCL_F32 && L <= 32) {
+        const pscl_launch_cfg lay = cur;
+        for (int fz : {-1, 3, 4, 5}) {
+            pscl_launch_cfg c = lay;
+            c.fuse_log2 = fz;
+            trial(c);
+        }
+    }
+    // 4. residency cap at the best so far (fewer frames per CU)
+    {
+        const pscl_launch_cfg lay = cur;
+        for (int cap : {2, 4, 8}) {
+            pscl_launch_cfg c = lay;
+            c.max_wg_per_cu = cap;
+            trial(c);
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -2785,8 +2917,90 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     (void)hipFree(ok);
     (void)hipFree(pm);
     if (st == PSCL_OK && best_t < 0.f) st = PSCL_E_UNSUPPORTED;
+    if (st == PSCL_OK) *best = cur;
     if (st == PSCL_OK && best_ms) *best_ms = best_t;
     return st;
+}
+
+pscl_status pscl_autotune_group(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
+                                int n_jobs, void* stream, pscl_launch_cfg* cfgs, int* threads,
+                                float* best_ms) {
+    if (!plans || n_plans < 1 || !jobs || n_jobs < 1 || !cfgs || !threads) return PSCL_E_INVALID;
+    for (int i = 0; i < n_plans; ++i)
+        if (!plans[i] || plans[i]->dtype != plans[0]->dtype) return PSCL_E_INVALID;
+    for (int j = 0; j < n_jobs; ++j)
+        if (jobs[j].plan < 0 || jobs[j].plan >= n_plans) return PSCL_E_INVALID;
+    const int dtype = plans[0]->dtype;
+    int max_L = 1;
+    for (int i = 0; i < n_plans; ++i) max_L = std::max(max_L, plans[i]->L);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pscl_status st = hip_status(hipEventCreate(&e0));
+    if (st == PSCL_OK) st = hip_status(hipEventCreate(&e1));
+    float best_t = -1.f;
+    pscl_launch_cfg cur{};
+    // one configuration for every plan of the group: plans rebuilt from the
+    // given plans' codes, a group of them, the jobs decoded once to warm up
+    // and twice timed
+    auto trial = [&](const pscl_launch_cfg& cfg) {
+        if (st != PSCL_OK) return;
+        if (cfg.threads < max_L && max_L > 64) return;  // at most 64 paths per wavefront
+        std::vector<pscl_plan*> tp(n_plans, nullptr);
+        pscl_status cs = PSCL_OK;
+        for (int i = 0; i < n_plans && cs == PSCL_OK; ++i) {
+            const pscl_plan* p = plans[i];
+            cs = pscl_plan_create_cfg(p->N, p->K, p->frozen.data(), p->poly, p->r, p->L, p->dtype,
+                                      p->spc_max, p->mode, &cfg, &tp[i]);
+        }
+        pscl_group* g = nullptr;
+        if (cs == PSCL_OK) {
+            pscl_launch_cfg gc{cfg.threads, 0, 0, 0, 0};
+            cs = pscl_group_create((const pscl_plan* const*)tp.data(), n_plans, n_jobs, 1, &gc, &g);
+        }
+        float ms = 0.f;
+        if (cs == PSCL_OK) cs = pscl_group_decode(g, jobs, n_jobs, stream);
+        if (cs == PSCL_OK) cs = hip_status(hipEventRecord(e0, s));
+        for (int r = 0; r < 2 && cs == PSCL_OK; ++r) cs = pscl_group_decode(g, jobs, n_jobs, stream);
+        if (cs == PSCL_OK) cs = hip_status(hipEventRecord(e1, s));
+        if (cs == PSCL_OK) cs = hip_status(hipEventSynchronize(e1));
+        if (cs == PSCL_OK) cs = hip_status(hipEventElapsedTime(&ms, e0, e1));
+        pscl_group_destroy(g);
+        for (pscl_plan* p : tp) pscl_plan_destroy(p);
+        if (cs == PSCL_E_UNSUPPORTED || cs == PSCL_E_NOMEM) return;
+        if (cs != PSCL_OK) {
+            st = cs;
+            return;
+        }
+        ms *= 0.5f;
+        if (best_t < 0.f || ms < best_t) {
+            best_t = ms;
+            cur = cfg;
+        }
+    };
+    for (int t : {64, 128, 256})
+        for (int b : {8192, 10240, 12288, 16384, 24576, 32768}) trial(pscl_launch_cfg{t, b, 0, 0, 0});
+    const pscl_launch_cfg shape = cur;
+    for (int rc = 1; rc <= 3; ++rc) {
+        pscl_launch_cfg c = shape;
+        c.recompute = rc;
+        trial(c);
+    }
+    if (dtype == PSCL_F32) {
+        const pscl_launch_cfg lay = cur;
+        for (int fz : {-1, 4, 5}) {
+            pscl_launch_cfg c = lay;
+            c.fuse_log2 = fz;
+            trial(c);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == PSCL_OK && best_t < 0.f) st = PSCL_E_UNSUPPORTED;
+    if (st != PSCL_OK) return st;
+    for (int i = 0; i < n_plans; ++i) cfgs[i] = cur;
+    *threads = cur.threads;
+    if (best_ms) *best_ms = best_t;
+    return PSCL_OK;
 }
 
 void pscl_group_destroy(pscl_group* g) {

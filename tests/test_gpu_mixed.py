@@ -73,9 +73,30 @@ def test_group_equals_single_plan_decodes(env, dtype):
         torch.cuda.synchronize()
         assert _same([o.cpu().numpy() for o in out], [a.cpu().numpy() for a in alone]), j
         code, L = codes[pi]
-        if code.N <= 2048:
-            ref = oracle_decode(code, L, host[j], dtype)
-            compare(tuple(o.cpu().numpy() for o in out), ref, dtype, f"mixed job {j}")
+        ref = oracle_decode(code, L, host[j], dtype)
+        compare(tuple(o.cpu().numpy() for o in out), ref, dtype, f"mixed job {j}")
+    g.close()
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_autotuned_group_against_oracle(env, dtype):
+    """pscl_autotune_group on a mixed batch, plans rebuilt with the tuned
+    configuration, one launch: every job matches the oracle."""
+    pk, torch = env
+    frames = [(0, 40), (1, 33), (2, 20), (3, 12), (4, 6)]
+    codes, plans, work, host = _setup(pk, torch, dtype, frames, 53)
+    cfgs, threads, ms = pk.autotune_group(plans, work)
+    _say(f"autotuned {dtype}: threads {threads}, cfg {cfgs[0]}, {ms:.3f} ms per call")
+    assert threads in (64, 128, 256) and len(cfgs) == len(plans)
+    tuned = [pk.Plan(c.N, c.K, c.frozen, c.poly, c.r, L, dtype, cfg=cfg)
+             for (c, L), cfg in zip(codes, cfgs)]
+    g = pk.Group(tuned, max_jobs=8, threads=threads)
+    outs = g.decode(work)
+    torch.cuda.synchronize()
+    for j, ((pi, llr), out) in enumerate(zip(work, outs)):
+        code, L = codes[pi]
+        ref = oracle_decode(code, L, host[j], dtype)
+        compare(tuple(o.cpu().numpy() for o in out), ref, dtype, f"autotuned job {j}")
     g.close()
 
 

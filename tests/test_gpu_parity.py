@@ -264,3 +264,42 @@ def test_autotuned_launch_shape():
     assert plan.info()["threads"] == cfg["threads"]
     g = gpu_decode(code, 8, b.llr, "i8", plan=plan)
     compare(g, oracle_decode(code, 8, b.llr, "i8"), "i8", "autotuned plan")
+
+
+# ---------------------------------------------------------------------------
+# Layout knobs: stages below the root stored or recomputed (none, one level,
+# two levels) and the size of forking leaves run fused (float32), each
+# against the oracle.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f32", "i16", "i8"])
+@pytest.mark.parametrize("recompute", [1, 2, 3])
+@pytest.mark.parametrize("nk", [(2048, 1723, 32, 4.0, 3.75), (1024, 512, 8, 2.5, 2.0),
+                                (256, 128, 8, 2.5, 2.0)])
+def test_recomputed_stages(dtype, recompute, nk):
+    import paper_1505_01466_amd as pk
+
+    N, K, r, d, e = nk
+    poly = synth.CRC32_POLY if r == 32 else synth.CRC8_POLY
+    code, b = batch(N, K, r, poly, d, 96, e, (61, N, recompute), dtype)
+    for budget in (0, 8192):  # default; small enough that the top levels spill
+        plan = pk.Plan(N, K, code.frozen, code.poly, r, 32, dtype, recompute=recompute,
+                       lds_budget=budget)
+        _say(f"({N},{K}) L=32 {dtype} recompute={recompute} budget={budget}: {plan.info()}")
+        g = gpu_decode(code, 32, b.llr, dtype, plan=plan)
+        compare(g, oracle_decode(code, 32, b.llr, dtype), dtype,
+                f"recompute={recompute} budget={budget}")
+        plan.close()
+
+
+@pytest.mark.parametrize("fuse", [-1, 1, 3, 4, 5])
+@pytest.mark.parametrize("L", [2, 8, 32])
+def test_fused_fork_sizes(fuse, L):
+    import paper_1505_01466_amd as pk
+
+    code, b = batch(1024, 860, 32, synth.CRC32_POLY, 4.0, 128, 3.5, (62, L, fuse + 1), "f32")
+    plan = pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "f32", fuse_log2=fuse)
+    _say(f"(1024,860) L={L} f32 fuse_log2={fuse}")
+    g = gpu_decode(code, L, b.llr, "f32", plan=plan)
+    compare(g, oracle_decode(code, L, b.llr, "f32"), "f32", f"fuse={fuse} L={L}")
+    plan.close()
