@@ -292,10 +292,12 @@ def quantile_ci(x, q, z=1.959964):
 def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), span_s=0.25,
                 max_requests=16000, streams=4):
     """Poisson arrivals of requests of 1..64 frames of a random code of the
-    mixed set (int8), replayed through a server on `streams` streams and as
-    plain per-request launches round-robin on as many streams (a set of
-    plans per stream); p50 / p99 latency (with order-statistic intervals)
-    and sustained payload Gbps."""
+    mixed set (int8), replayed through a server launching batches on
+    `streams` streams, through a persistent-mode server (one persistent
+    kernel consuming a request ring; with as many workgroups per CU as fit,
+    and with at most 4), and as plain per-request launches
+    round-robin on `streams` streams (a set of plans per stream); p50 / p99
+    latency (with order-statistic intervals) and sustained payload Gbps."""
     codes = c4_codes(synth)
     sets = [[pk.Plan(code.N, code.K, code.frozen, code.poly, code.r, L, "i8")
              for code, L, _ in codes] for _ in range(streams)]
@@ -315,9 +317,12 @@ def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), s
         work = [(int(i), pool[int(i)][: int(f)]) for i, f in zip(idx, F)]
         bits = float(sum(payload[int(i)] * int(f) for i, f in zip(idx, F)))
         row = {"requests": n, "arrival_span_s": round(float(arrivals[-1]) * 1e-6, 4)}
-        for name in ("server", "per_request"):
+        for name in ("server", "persistent", "persistent_4_per_cu", "per_request"):
             if name == "server":
                 sv = pk.Server(plans, streams=streams)
+                _, lat, el = pk.replay(plans, work, arrivals, server=sv)
+            elif name.startswith("persistent"):
+                sv = pk.Server(plans, persistent=True, wg_per_cu=4 if name.endswith("cu") else 0)
                 _, lat, el = pk.replay(plans, work, arrivals, server=sv)
             else:
                 sv = None

@@ -188,6 +188,10 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
 /* Release a plan (NULL allowed).  Synchronises the device first. */
 void pscl_plan_destroy(pscl_plan* plan);
 
+/* The code and list a plan decodes (each output pointer may be NULL). */
+pscl_status pscl_plan_code(const pscl_plan* plan, int* N, int* K, int* crc_len, int* L,
+                           int* dtype);
+
 /* Device bytes one frame of the plan occupies while it is decoded: its
  * global workspace and LDS, its LLR row and its outputs (K + 1 + 4 bytes).
  * Servers charge requests F times this against their admission budget. */
@@ -340,6 +344,21 @@ pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const 
  * submission (or, in pscl_replay, the scheduled arrival) to the moment the
  * dispatcher sees the launch that decoded it complete.
  *
+ * Persistent mode (cfg.persistent = 1): instead of a launch per batch, the
+ * dispatcher publishes each request, once its inputs are ready, into a ring
+ * in coherent host memory (a record per frame: its rows, its request's
+ * slot, ticket, plan and size; the count of published frames), and one
+ * persistent kernel on the
+ * server's stream, with as many workgroups as it can keep resident,
+ * claims published frames one at a time and decodes them, so a request
+ * starts as soon as any workgroup is free (continuous batching at frame
+ * granularity); the last frame of a request writes its ticket to the
+ * request's completion word.  The kernel ends after idle_us microseconds
+ * without work (so it never outlives the server) and is relaunched when
+ * requests are held.  `streams`, max_batch_frames and max_batch_requests
+ * do not apply; at most 2^18 frames are published and unfinished at once
+ * (a larger request is invalid, more are held back).
+ *
  * Admission (pscl_server_submit returns PSCL_E_BUSY, the caller retries):
  * by request count, by queued frames, and by device footprint: a request of
  * F frames of plan p is charged F * pscl_plan_footprint(p) bytes from its
@@ -357,6 +376,11 @@ typedef struct {
     int64_t max_batch_frames;   /* frames per launch (0 = no limit; one request at least) */
     int max_batch_requests;     /* requests per launch (0 = 1024) */
     int64_t max_footprint_bytes; /* device bytes of held requests (0 = no limit) */
+    int persistent; /* 1 = persistent mode (below); 0 = launches per batch */
+    int idle_us;    /* persistent mode: a launch ends after this long without work
+                       (0 = 2000) */
+    int wg_per_cu;  /* persistent mode: resident workgroups per CU at most (0 = as
+                       many as fit) */
 } pscl_server_cfg;
 
 /* Create a server on the current device (allocates one group, stream and

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "pscl.h"
+#include "ring.h"
 #include "schedule.h"
 
 namespace pscl {
@@ -1656,7 +1657,16 @@ DEV uint64_t word_syndrome(uint32_t v, const uint64_t* sy, int nb) {
     return acc;
 }
 
-template <typename T, int RSP, bool WIDE>
+// Output stores: plain, or (SYS) system-scope stores that write through the
+// L2, so that a persistent kernel's outputs reach memory without a cache
+// write-back.
+template <bool SYS, typename V>
+DEV void out_store(V* p, V v) {
+    if constexpr (SYS) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    else *p = v;
+}
+
+template <typename T, int RSP, bool WIDE, bool SYS = false>
 DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_hat,
                 uint8_t* crc_ok, void* pm_out) {
     using D = Dom<T>;
@@ -1767,8 +1777,8 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
     }
     if (c.tid == 0) {
         const int best = si[0];
-        if (crc_ok) crc_ok[f] = (uint8_t)si[1];
-        if (pm_out) ((uint32_t*)pm_out)[f] = D::bits(c.pm()[best]);
+        if (crc_ok) out_store<SYS>(crc_ok + f, (uint8_t)si[1]);
+        if (pm_out) out_store<SYS>((uint32_t*)pm_out + f, (uint32_t)D::bits(c.pm()[best]));
     }
     __syncthreads();
     // u = x G_N on the chosen codeword, in place: bits within words ...
@@ -1797,7 +1807,7 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
         const int K = a.K;
         for (int t = c.tid; t < K; t += c.NT) {
             const int p = a.info_pos[t];
-            u_hat[f * K + t] = (uint8_t)((x[p >> 5] >> (p & 31)) & 1u);
+            out_store<SYS>(u_hat + f * K + t, (uint8_t)((x[p >> 5] >> (p & 31)) & 1u));
         }
     }
 }
@@ -1827,7 +1837,7 @@ DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
 // Schedule records are read with scalar loads (sched points into a
 // read-only kernel argument), the next one while the current operation
 // runs.  Outputs go to entry f of u_hat / crc_ok / pm_out.
-template <typename T, bool WIDE>
+template <typename T, bool WIDE, bool SYS = false>
 DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sched, int64_t f,
                       uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                       void* __restrict__ pm_out) {
@@ -1910,8 +1920,8 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
     }
     if (pend) pp_emit_pending<T>(c, pop, pprune, q);
     __syncthreads();
-    if (a.root_sp == SP_LDS) finish<T, SP_LDS, WIDE>(c, a, P, f, u_hat, crc_ok, pm_out);
-    else finish<T, SP_WS, WIDE>(c, a, P, f, u_hat, crc_ok, pm_out);
+    if (a.root_sp == SP_LDS) finish<T, SP_LDS, WIDE, SYS>(c, a, P, f, u_hat, crc_ok, pm_out);
+    else finish<T, SP_WS, WIDE, SYS>(c, a, P, f, u_hat, crc_ok, pm_out);
     __syncthreads();
 }
 
@@ -2011,6 +2021,133 @@ __global__ void __launch_bounds__(1024)
 }
 
 __global__ void zero_counter(unsigned long long* counter) { *counter = 0ull; }
+
+// ---------------------------------------------------------------------------
+// Persistent serving: workgroups claim published frames of a request ring
+// (ring.h) until the host stops them or no frame arrives for idle_us.
+// ---------------------------------------------------------------------------
+
+DEV uint64_t ld_sys(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+DEV uint32_t ld_sys(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// A ticket: the next frame left unclaimed by the previous launch, else a
+// new frame number.
+DEV int64_t ring_ticket(const pscl_ring::Args& r) {
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    pscl_ring::Dev* dv = r.dev;
+    const uint32_t prev = r.parity ^ 1u;
+    const uint32_t n = __hip_atomic_load(&dv->orphan_n[prev], __ATOMIC_RELAXED, AG);
+    if (__hip_atomic_load(&dv->orphan_take[prev], __ATOMIC_RELAXED, AG) < n) {
+        const uint32_t k = __hip_atomic_fetch_add(&dv->orphan_take[prev], 1u, __ATOMIC_RELAXED, AG);
+        if (k < n) return (int64_t)r.orphans[(uint64_t)prev * r.orphan_cap + k];
+    }
+    return (int64_t)__hip_atomic_fetch_add(&dv->next, 1ull, __ATOMIC_RELAXED, AG);
+}
+
+// Waits until frame t is published: 1 then, 0 when the host has raised stop
+// or nothing new was published for idle_us (the real-time counter runs at
+// 100 MHz; the number of polls is bounded as well).  Host memory is read
+// by one idle workgroup at a time; the others poll its device copy, less
+// often the further their frame is from the published count.
+DEV int ring_wait(const pscl_ring::Args& r, uint64_t t) {
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    pscl_ring::Dev* dv = r.dev;
+    uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    const uint64_t idle = (uint64_t)r.idle_us * 100u;
+    const uint32_t max_polls = r.idle_us + 64u;
+    unsigned long long last = __hip_atomic_load(&dv->published, __ATOMIC_ACQUIRE, AG);
+    for (uint32_t poll = 0;; ++poll) {
+        unsigned long long pub = __hip_atomic_load(&dv->published, __ATOMIC_ACQUIRE, AG);
+        if (pub <= t && __hip_atomic_load(&dv->lease, __ATOMIC_RELAXED, AG) == 0u &&
+            __hip_atomic_exchange(&dv->lease, 1u, __ATOMIC_ACQUIRE, AG) == 0u) {
+            const uint64_t hp =
+                __hip_atomic_load(&r.ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ld_sys(&r.ctl->stop)) __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELAXED, AG);
+            __hip_atomic_fetch_max(&dv->published, (unsigned long long)hp, __ATOMIC_RELEASE, AG);
+            __hip_atomic_store(&dv->lease, 0u, __ATOMIC_RELEASE, AG);
+            pub = hp > pub ? hp : pub;
+        }
+        if (pub > t) return 1;
+        if (__hip_atomic_load(&dv->stop, __ATOMIC_RELAXED, AG)) return 0;
+        if (pub != last) {  // progress: the idle clock restarts
+            last = pub;
+            t0 = __builtin_amdgcn_s_memrealtime();
+            poll = 0;
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > idle || poll >= max_polls) return 0;
+        // about 3.4 us per sleep, more when the frame is far ahead
+        const uint64_t ahead = t - pub;
+        const int naps = ahead < 256 ? 1 : (ahead < 4096 ? 2 : 4);
+        for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
+    }
+}
+
+template <typename T, bool WIDE>
+__global__ void __launch_bounds__(1024)
+    serve_kernel(const DevPlan* __restrict__ plans, const uint64_t* __restrict__ sched,
+                 uint8_t* __restrict__ ws, int64_t ws_frame, pscl_ring::Args r) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ long long slot;
+    __shared__ pscl_ring::Rec d;
+    Ctx<T> c;
+    c.lds = lds;
+    c.tid = threadIdx.x;
+    c.NT = blockDim.x;
+    c.lane = threadIdx.x & 63;
+    uint8_t* wsb = ws + (int64_t)blockIdx.x * ws_frame;
+    for (;;) {
+        if (c.tid == 0) {
+            const int64_t t = ring_ticket(r);
+            int64_t g = t;
+            if (!ring_wait(r, (uint64_t)t)) {
+                // leaving with an unpublished frame: the next launch takes it
+                const uint32_t k = __hip_atomic_fetch_add(&r.dev->orphan_n[r.parity], 1u,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                r.orphans[(uint64_t)r.parity * r.orphan_cap + k] = (unsigned long long)t;
+                g = -1;
+            }
+            slot = g;
+        }
+        __syncthreads();
+        const int64_t g = slot;
+        if (g < 0) break;
+        // the frame's record: eight words read from host memory by eight
+        // lanes in one load
+        static_assert(sizeof(pscl_ring::Rec) == 8 * sizeof(uint64_t), "record of eight words");
+        if (c.tid < 8) {
+            const uint64_t* w = (const uint64_t*)(r.rec + ((uint64_t)g & r.rec_mask));
+            ((uint64_t*)&d)[c.tid] = ld_sys(w + c.tid);
+        }
+        __syncthreads();
+        const DevPlan& D = plans[d.plan];
+        const KArgs a = D.a;
+        bind_plan(c, a, wsb);
+        c.chan = (const T*)d.llr;
+        decode_frame<T, WIDE>(c, a, sched + D.op_base, 0, d.u_hat, d.crc_ok, d.pm);
+        // every thread's outputs of the frame written back and visible to
+        // the host and other agents before the count
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __syncthreads();
+        if (c.tid == 0) {
+            const uint32_t s = d.slot;
+            const uint32_t prev =
+                __hip_atomic_fetch_add(r.count + s, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int64_t)prev + 1 == d.F) {
+                // the request's last frame: reset the slot's count, then
+                // report the ticket
+                __hip_atomic_store(r.count + s, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                __hip_atomic_store(r.done + s, d.ticket, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();
+    }
+}
 
 // Device memory of pscl_decode_noalloc: the frame counter in the first 256
 // bytes, then the global workspaces of as many workgroups as fit.  One copy
@@ -2151,6 +2288,31 @@ void launch_mixed(const pscl_group* g, int slot, int grid, int nj, int64_t total
             hipLaunchKernelGGL((decode_mixed_kernel<int8_t, W>), dim3(grid), dim3(g->NT),
                                g->lds_bytes, s, g->d_plans, g->d_jobs[slot], nj, total, g->d_sched,
                                g->d_ws[slot], g->ws_frame, g->d_counter[slot]);
+            break;
+    }
+}
+
+template <bool W>
+const void* serve_kernel_for(int dtype) {
+    return dtype == PSCL_F32   ? (const void*)&serve_kernel<float, W>
+           : dtype == PSCL_I16 ? (const void*)&serve_kernel<int16_t, W>
+                               : (const void*)&serve_kernel<int8_t, W>;
+}
+
+template <bool W>
+void launch_serve(const pscl_group* g, int grid, const pscl_ring::Args& r, hipStream_t s) {
+    switch (g->dtype) {
+        case PSCL_F32:
+            hipLaunchKernelGGL((serve_kernel<float, W>), dim3(grid), dim3(g->NT), g->lds_bytes, s,
+                               g->d_plans, g->d_sched, g->d_ws[0], g->ws_frame, r);
+            break;
+        case PSCL_I16:
+            hipLaunchKernelGGL((serve_kernel<int16_t, W>), dim3(grid), dim3(g->NT), g->lds_bytes,
+                               s, g->d_plans, g->d_sched, g->d_ws[0], g->ws_frame, r);
+            break;
+        default:
+            hipLaunchKernelGGL((serve_kernel<int8_t, W>), dim3(grid), dim3(g->NT), g->lds_bytes,
+                               s, g->d_plans, g->d_sched, g->d_ws[0], g->ws_frame, r);
             break;
     }
 }
@@ -2718,6 +2880,17 @@ pscl_status pscl_plan_info(const pscl_plan* p, int* frames_per_wg, int* threads,
     return PSCL_OK;
 }
 
+pscl_status pscl_plan_code(const pscl_plan* p, int* N, int* K, int* crc_len, int* L,
+                           int* dtype) {
+    if (!p) return PSCL_E_INVALID;
+    if (N) *N = p->N;
+    if (K) *K = p->K;
+    if (crc_len) *crc_len = p->r;
+    if (L) *L = p->L;
+    if (dtype) *dtype = p->dtype;
+    return PSCL_OK;
+}
+
 pscl_status pscl_plan_footprint(const pscl_plan* p, int64_t* bytes_per_frame) {
     if (!p || !bytes_per_frame) return PSCL_E_INVALID;
     *bytes_per_frame = p->args.ws_frame + p->lds_bytes + (int64_t)p->N * elem_size(p->dtype) +
@@ -3164,6 +3337,38 @@ pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, v
     g->used[slot] = 1;
     return PSCL_OK;
 }
+
+}  // extern "C"
+
+// The persistent serving kernel of a group's plans (ring.h): as many
+// workgroups as the kernel can keep resident, at most the group's grid (the
+// group's first workspace has that many slots).
+pscl_status pscl_ring::launch(pscl_group* g, const pscl_ring::Args& r, hipStream_t s) {
+    if (!g || !r.ctl || !r.rec || !r.done || !r.count || !r.dev || !r.orphans)
+        return PSCL_E_INVALID;
+    const void* kern = g->wide ? serve_kernel_for<true>(g->dtype) : serve_kernel_for<false>(g->dtype);
+    pscl_status st = hip_status(
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, g->lds_bytes));
+    int occ = 0, cus = 0;
+    if (st == PSCL_OK)
+        st = hip_status(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, g->NT, g->lds_bytes));
+    if (st == PSCL_OK)
+        st = hip_status(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+    if (st != PSCL_OK) return st;
+    if (occ < 1) return PSCL_E_UNSUPPORTED;
+    if (r.wg_per_cu > 0) occ = std::min(occ, (int)r.wg_per_cu);
+    const int grid = std::min<int>(std::min(g->grid, occ * cus), (int)r.orphan_cap);
+    // this launch's orphan list and the previous one's take count start at 0
+    pscl_ring::Dev* dv = r.dev;
+    if (hipMemsetAsync(&dv->orphan_n[r.parity], 0, 4, s) != hipSuccess ||
+        hipMemsetAsync(&dv->orphan_take[r.parity ^ 1u], 0, 4, s) != hipSuccess)
+        return PSCL_E_HIP;
+    if (g->wide) launch_serve<true>(g, grid, r, s);
+    else launch_serve<false>(g, grid, r, s);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" {
 
 pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const pscl_job* jobs,
                               int n_jobs, void* stream) {

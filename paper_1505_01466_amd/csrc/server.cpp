@@ -1,9 +1,15 @@
-// Serving loop: requests (one pscl_job each) decoded as they arrive, by a
-// dispatcher thread that keeps up to S mixed launches in flight, one per
-// stream, and whenever a stream is free launches every pending request as
-// one batch (continuous batching).  Built on the public group API; each
-// stream owns a group with one call in flight, so no two launches share a
-// workspace.  A replay driver submits a request trace at given arrival times
+// Serving loop: requests (one pscl_job each) decoded as they arrive.  Two
+// modes:
+//  - launches: a dispatcher thread keeps up to S mixed launches in flight,
+//    one per stream, and whenever a stream is free launches every pending
+//    request as one batch (continuous batching at launch granularity).
+//    Built on the public group API; each stream owns a group with one call
+//    in flight, so no two launches share a workspace.
+//  - persistent: the dispatcher publishes requests into a ring in coherent
+//    host memory (ring.h) that a persistent kernel consumes frame by frame
+//    (continuous batching at frame granularity, no launch per batch); the
+//    kernel leaves after a spell without work and is relaunched when
+//    requests are held and no launch runs.  A replay driver submits a request trace at given arrival times
 // through a server, or as plain per-request pscl_decode launches (the
 // baseline), and reports per-request latencies.
 
@@ -13,6 +19,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <thread>
@@ -20,6 +27,7 @@
 #include <vector>
 
 #include "pscl.h"
+#include "ring.h"
 
 namespace {
 
@@ -76,13 +84,40 @@ struct pscl_server {
     int64_t n_req = 0, n_frames = 0, n_launch = 0;
     std::thread th;
 
+    // persistent mode
+    bool ring = false;
+    pscl_group* rgroup = nullptr;
+    hipStream_t rstream = nullptr;
+    hipEvent_t rev = nullptr;  // end of the current launch
+    bool rlaunched = false;
+    pscl_ring::Ctl* ctl = nullptr;
+    pscl_ring::Rec* rec = nullptr;
+    uint64_t* rdone = nullptr;
+    uint32_t* rcount = nullptr;
+    pscl_ring::Dev* rdev = nullptr;
+    unsigned long long* rorphans = nullptr;
+    pscl_ring::Args rargs{};
+    int64_t rec_size = 0;
+    std::vector<int64_t> row_in, row_out;  // LLR row bytes and K per plan
+    int64_t ring_frames = 0;  // published and not finished
+    uint64_t published = 0;
+    uint32_t idle_us = 2000;
+    std::vector<int> free_slots;
+    std::vector<Req> slot_req;
+    std::vector<int> busy_slots;
+
     void run();
+    void run_ring();
     pscl_status submit(const pscl_job& job, hipStream_t ready_on, bool order, double t_arrive,
                        double* sink, uint64_t* ticket);
 };
 
 void pscl_server::run() {
     (void)hipSetDevice(device);
+    if (ring) {
+        run_ring();
+        return;
+    }
     std::vector<pscl_job> jobs;
     for (;;) {
         bool progress = false;
@@ -165,6 +200,110 @@ void pscl_server::run() {
     }
 }
 
+// Persistent mode: completions are read from the ring's completion words;
+// pending requests whose inputs are ready are published in order while ring
+// slots and frame-map entries are free; a launch is started whenever
+// requests are held and none runs.
+void pscl_server::run_ring() {
+    for (;;) {
+        bool progress = false;
+        // completions
+        for (size_t i = 0; i < busy_slots.size();) {
+            const int sl = busy_slots[i];
+            const Req& r = slot_req[sl];
+            if (__atomic_load_n(&rdone[sl], __ATOMIC_ACQUIRE) != r.ticket) {
+                ++i;
+                continue;
+            }
+            const double t = now_us();
+            std::lock_guard<std::mutex> lk(mu);
+            const double l = t - r.t_arrive;
+            if (r.sink) *r.sink = l;
+            else done[r.ticket] = l;
+            lat.push_back(l);
+            n_req += 1;
+            n_frames += r.job.F;
+            held -= 1;
+            held_footprint -= r.footprint;
+            ring_frames -= r.job.F;
+            if (r.ready) free_events.push_back(r.ready);
+            free_slots.push_back(sl);
+            busy_slots[i] = busy_slots.back();
+            busy_slots.pop_back();
+            progress = true;
+            cv_done.notify_all();
+        }
+        // publication
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            while (!pending.empty() && !free_slots.empty()) {
+                const Req& r = pending.front();
+                if (ring_frames + r.job.F > rec_size) break;
+                if (r.ready) {
+                    const hipError_t q = hipEventQuery(r.ready);
+                    if (q == hipErrorNotReady) break;
+                    if (q != hipSuccess && error == PSCL_OK) error = PSCL_E_HIP;
+                }
+                const int sl = free_slots.back();
+                free_slots.pop_back();
+                slot_req[sl] = r;
+                const pscl_job& J = r.job;
+                const int64_t in = row_in[J.plan], out = row_out[J.plan];
+                for (int64_t f = 0; f < J.F; ++f) {
+                    pscl_ring::Rec& d = rec[(published + (uint64_t)f) & (uint64_t)(rec_size - 1)];
+                    d.llr = (const uint8_t*)J.llr + f * in;
+                    d.u_hat = J.u_hat + f * out;
+                    d.crc_ok = J.crc_ok ? J.crc_ok + f : nullptr;
+                    d.pm = J.pm ? (void*)((uint8_t*)J.pm + f * 4) : nullptr;
+                    d.ticket = r.ticket;
+                    d.slot = (uint32_t)sl;
+                    d.plan = J.plan;
+                    d.F = J.F;
+                    d.pad = 0;
+                }
+                published += (uint64_t)J.F;
+                // the records before the count that publishes them
+                __atomic_store_n(&ctl->published, published, __ATOMIC_RELEASE);
+                ring_frames += r.job.F;
+                pending_frames -= r.job.F;
+                busy_slots.push_back(sl);
+                pending.pop_front();
+                progress = true;
+            }
+        }
+        // a launch while requests are held
+        if (!busy_slots.empty()) {
+            bool running = rlaunched && hipEventQuery(rev) == hipErrorNotReady;
+            if (!running) {
+                rargs.parity = (uint32_t)(n_launch & 1);
+                pscl_status st = pscl_ring::launch(rgroup, rargs, rstream);
+                if (st == PSCL_OK && hipEventRecord(rev, rstream) != hipSuccess) st = PSCL_E_HIP;
+                std::lock_guard<std::mutex> lk(mu);
+                if (st != PSCL_OK) {
+                    if (error == PSCL_OK) error = st;
+                } else {
+                    rlaunched = true;
+                    n_launch += 1;
+                }
+                progress = true;
+            }
+        }
+        std::unique_lock<std::mutex> lk(mu);
+        if (error != PSCL_OK) {
+            // nothing more can complete: release the waiters
+            cv_done.notify_all();
+            if (stop) return;
+        }
+        if (busy_slots.empty() && pending.empty()) {
+            if (stop) return;
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        } else if (!progress) {
+            lk.unlock();
+            std::this_thread::yield();
+        }
+    }
+}
+
 pscl_status pscl_server::submit(const pscl_job& job, hipStream_t ready_on, bool order,
                                  double t_arrive, double* sink, uint64_t* ticket) {
     if (job.plan < 0 || job.plan >= (int)plans.size() || job.F < 0) return PSCL_E_INVALID;
@@ -173,6 +312,7 @@ pscl_status pscl_server::submit(const pscl_job& job, hipStream_t ready_on, bool 
     if (max_pending_frames > 0 && job.F > max_pending_frames) return PSCL_E_INVALID;  // never fits
     const int64_t fp = job.F * frame_bytes[job.plan];
     if (max_footprint > 0 && fp > max_footprint) return PSCL_E_INVALID;  // never fits
+    if (ring && job.F > rec_size) return PSCL_E_INVALID;  // never fits the frame records
     hipEvent_t ev = nullptr;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -220,6 +360,70 @@ pscl_status pscl_server::submit(const pscl_job& job, hipStream_t ready_on, bool 
     return PSCL_OK;
 }
 
+// Persistent mode: one group for the workspace and plan tables, a stream
+// and an end event for the launches, the ring in coherent host memory
+// (frame records, completion words per slot, the control block) and the
+// device counters.
+static pscl_status ring_setup(pscl_server* sv, const pscl_server_cfg* cfg) {
+    pscl_status st = pscl_group_create(cfg->plans, cfg->n_plans, 1, 1, nullptr, &sv->rgroup);
+    if (st != PSCL_OK) return st;
+    const int R = sv->max_requests;
+    sv->rec_size = int64_t(1) << 18;
+    for (int i = 0; i < cfg->n_plans; ++i) {
+        int N = 0, K = 0, dt = 0;
+        st = pscl_plan_code(cfg->plans[i], &N, &K, nullptr, nullptr, &dt);
+        if (st != PSCL_OK) return st;
+        sv->row_in.push_back((int64_t)N * (dt == PSCL_F32 ? 4 : (dt == PSCL_I16 ? 2 : 1)));
+        sv->row_out.push_back(K);
+    }
+    auto hmalloc = [&](void** p, size_t bytes) {
+        if (st != PSCL_OK) return;
+        if (hipHostMalloc(p, bytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            *p = nullptr;
+            st = PSCL_E_NOMEM;
+            return;
+        }
+        memset(*p, 0, bytes);
+    };
+    hmalloc((void**)&sv->ctl, sizeof(pscl_ring::Ctl));
+    hmalloc((void**)&sv->rec, sizeof(pscl_ring::Rec) * (size_t)sv->rec_size);
+    hmalloc((void**)&sv->rdone, sizeof(uint64_t) * (size_t)R);
+    if (st != PSCL_OK) return st;
+    if (hipMalloc((void**)&sv->rcount, sizeof(uint32_t) * (size_t)R) != hipSuccess ||
+        hipMalloc((void**)&sv->rdev, sizeof(pscl_ring::Dev)) != hipSuccess)
+        return PSCL_E_NOMEM;
+    // orphan lists: at most one ticket per workgroup per launch
+    const uint32_t cap = 1u << 16;
+    if (hipMalloc((void**)&sv->rorphans, sizeof(unsigned long long) * 2 * cap) != hipSuccess)
+        return PSCL_E_NOMEM;
+    if (hipMemset(sv->rcount, 0, sizeof(uint32_t) * (size_t)R) != hipSuccess ||
+        hipMemset(sv->rdev, 0, sizeof(pscl_ring::Dev)) != hipSuccess ||
+        hipStreamCreateWithFlags(&sv->rstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->rev, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return PSCL_E_HIP;
+    pscl_ring::Args& a = sv->rargs;
+    void* dp = nullptr;
+    auto dev_ptr = [&](void* h) {
+        if (st == PSCL_OK && hipHostGetDevicePointer(&dp, h, 0) != hipSuccess) st = PSCL_E_HIP;
+        return dp;
+    };
+    a.ctl = (pscl_ring::Ctl*)dev_ptr(sv->ctl);
+    a.rec = (const pscl_ring::Rec*)dev_ptr(sv->rec);
+    a.done = (uint64_t*)dev_ptr(sv->rdone);
+    a.count = sv->rcount;
+    a.dev = sv->rdev;
+    a.orphans = sv->rorphans;
+    a.orphan_cap = cap;
+    a.parity = 0;
+    a.rec_mask = (uint32_t)(sv->rec_size - 1);
+    a.idle_us = sv->idle_us;
+    a.wg_per_cu = (uint32_t)cfg->wg_per_cu;
+    sv->slot_req.resize((size_t)R);
+    for (int i = R - 1; i >= 0; --i) sv->free_slots.push_back(i);
+    return st;
+}
+
 extern "C" {
 
 void pscl_server_destroy(pscl_server* sv) {
@@ -232,6 +436,17 @@ void pscl_server_destroy(pscl_server* sv) {
         sv->cv_work.notify_all();
         sv->th.join();
     }
+    if (sv->ctl) __atomic_store_n(&sv->ctl->stop, 1u, __ATOMIC_RELEASE);
+    if (sv->rlaunched) (void)hipEventSynchronize(sv->rev);
+    if (sv->rstream) (void)hipStreamSynchronize(sv->rstream);
+    pscl_group_destroy(sv->rgroup);
+    if (sv->rev) (void)hipEventDestroy(sv->rev);
+    if (sv->rstream) (void)hipStreamDestroy(sv->rstream);
+    for (void* h : {(void*)sv->ctl, (void*)sv->rec, (void*)sv->rdone})
+        if (h) (void)hipHostFree(h);
+    (void)hipFree(sv->rcount);
+    (void)hipFree(sv->rdev);
+    (void)hipFree(sv->rorphans);
     for (pscl_group* g : sv->groups) pscl_group_destroy(g);
     for (hipEvent_t e : sv->ev)
         if (e) (void)hipEventDestroy(e);
@@ -245,7 +460,8 @@ pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
     if (!cfg || !out || !cfg->plans || cfg->n_plans < 1) return PSCL_E_INVALID;
     if (cfg->streams < 0 || cfg->streams > 8 || cfg->max_requests < 0 ||
         cfg->max_pending_frames < 0 || cfg->max_batch_frames < 0 || cfg->max_batch_requests < 0 ||
-        cfg->max_footprint_bytes < 0)
+        cfg->max_footprint_bytes < 0 || cfg->persistent < 0 || cfg->persistent > 1 ||
+        cfg->idle_us < 0 || cfg->wg_per_cu < 0)
         return PSCL_E_INVALID;
     for (int i = 0; i < cfg->n_plans; ++i)
         if (!cfg->plans[i]) return PSCL_E_INVALID;
@@ -266,6 +482,18 @@ pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
         int64_t b = 0;
         st = pscl_plan_footprint(cfg->plans[i], &b);
         sv->frame_bytes.push_back(b);
+    }
+    sv->ring = cfg->persistent == 1;
+    if (sv->ring) {
+        if (cfg->idle_us) sv->idle_us = (uint32_t)cfg->idle_us;
+        st = ring_setup(sv, cfg);
+        if (st != PSCL_OK) {
+            pscl_server_destroy(sv);
+            return st;
+        }
+        sv->th = std::thread([sv] { sv->run(); });
+        *out = sv;
+        return PSCL_OK;
     }
     for (int s = 0; s < sv->S && st == PSCL_OK; ++s) {
         pscl_group* g = nullptr;

@@ -262,3 +262,103 @@ def test_wait_with_time_limit(env):
     torch.cuda.synchronize()
     _check([out], _alone(torch, plans, [(2, llr)]))
     sv.close()
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_persistent_server_results_equal_alone(env, dtype):
+    """Persistent mode: requests published into the ring and decoded by a
+    persistent kernel, submitted in bursts with pauses longer than the
+    kernel's idle time (so it ends and is relaunched): every request equals
+    decoding it alone."""
+    import time
+
+    pk, torch, codes, plans = env
+    if dtype != "i8":
+        plans = [pk.Plan(c.N, c.K, c.frozen, c.poly, c.r, spec[5], dtype)
+                 for c, spec in zip(codes, CODES)]
+    rng = np.random.default_rng(101)
+    work = []
+    for i in range(90):
+        pi = int(rng.integers(len(codes)))
+        b = synth.make_batch(codes[pi], int(rng.integers(1, 65)), CODES[pi][4], (101, i), dtype)
+        work.append((pi, torch.from_numpy(b.llr).cuda()))
+    ref = _alone(torch, plans, work)
+    sv = pk.Server(plans, persistent=True, idle_us=500)
+    tickets = []
+    for burst in range(3):
+        for pi, llr in work[burst * 30:(burst + 1) * 30]:
+            tickets.append(sv.submit(pi, llr))
+        for t, _ in tickets[burst * 30:]:
+            sv.wait(t, timeout_ms=60000.0)
+        time.sleep(0.01)  # the kernel goes idle and ends
+    torch.cuda.synchronize()
+    _check([o for _, o in tickets], ref)
+    st = sv.stats()
+    _say(f"persistent server {dtype}: {st}")
+    assert st["requests"] == 90 and st["launches"] >= 3
+    sv.close()
+
+
+def test_persistent_server_replay_and_producer_order(env):
+    """Persistent mode through the replay driver (Poisson arrivals), and a
+    request whose inputs are still being generated when it is submitted."""
+    pk, torch, codes, plans = env
+    n = 200
+    work = _requests(torch, codes, n, 12)
+    ref = _alone(torch, plans, work)
+    rng = np.random.default_rng(4)
+    arrivals = np.cumsum(rng.exponential(1e6 / 20000.0, n))
+    sv = pk.Server(plans, persistent=True)
+    outs, lat, elapsed = pk.replay(plans, work, arrivals, server=sv)
+    torch.cuda.synchronize()
+    _check(outs, ref)
+    _say(f"persistent replay: p50 {np.percentile(lat, 50):.0f} us, "
+         f"p99 {np.percentile(lat, 99):.0f} us, launches {sv.stats()['launches']}")
+    code = codes[3]
+    gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, "i8")
+    llr = torch.zeros((256, code.N), dtype=torch.int8, device="cuda")
+    x = torch.randn(2048, 2048, device="cuda")
+    torch.cuda.synchronize()
+    for _ in range(30):
+        x = torch.tanh(x @ x) * 0.5
+    gen.generate(256, 4.0, 98, llr=llr)
+    t, out = sv.submit(3, llr)
+    sv.wait(t, timeout_ms=60000.0)
+    torch.cuda.synchronize()
+    _check([out], _alone(torch, plans, [(3, llr)]))
+    sv.close()
+    gen.close()
+
+
+def test_persistent_server_wraps_the_frame_records(env):
+    """More frames through one persistent-mode server than its ring holds
+    frame records (2^18), so every record position is reused, including
+    the last: every request equals decoding it alone."""
+    pk, torch, codes, plans = env
+    code = codes[0]  # (256,128) L = 2: cheap frames
+    b = synth.make_batch(code, 64, CODES[0][4], (202, 0), "i8")
+    llr = torch.from_numpy(b.llr).cuda()
+    ref = _alone(torch, plans, [(0, llr)])[0]
+    sv = pk.Server(plans, persistent=True, max_requests=2048)
+    n_req = (1 << 18) // 64 + 700  # 4,796 requests of 64 frames
+    outs, live = [], []
+    for i in range(n_req):
+        while True:
+            try:
+                t, out = sv.submit(0, llr)
+                break
+            except pk.PsclError as e:
+                assert e.status == 6
+                sv.wait(live.pop(0)[0], timeout_ms=60000.0)
+        live.append((t, out))
+        outs.append(out)
+    for t, _ in live:
+        sv.wait(t, timeout_ms=60000.0)
+    torch.cuda.synchronize()
+    for i in range(0, n_req, 97):
+        _check([outs[i]], [ref])
+    _check([outs[-1]], [ref])
+    st = sv.stats()
+    _say(f"persistent server, {n_req * 64} frames: {st}")
+    assert st["frames"] == n_req * 64
+    sv.close()
