@@ -95,19 +95,40 @@ def test_crc_pick_below_the_best_metric(dtype):
     assert o[1][frames].all()  # each of those frames does find a passing path
 
 
+def _wilson(k, n, z=1.959964):
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * ((p * (1 - p) / n + z * z / (4 * n * n)) ** 0.5) / d
+    return max(0.0, c - h), min(1.0, c + h)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_1024_512_crc8_L4_f32(mode):
-    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 2000, 2.5, (1, mode), "f32")
-    _say(f"(1024,512) L=4 f32 mode={mode}")
+    """The (1024,512) CRC-8 L = 4 workload at 2.5 dB, its full 10,000
+    frames: element by element against decoder A in both tree modes; the
+    unrolled SC-list mode also element by element against the bit-by-bit
+    SC-list decoder B, and the Dec-SPC-4 tree's frame error rate inside
+    decoder B's 95 % interval widened by its own (overlapping intervals)."""
+    import oracle
+
+    code, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 10000, 2.5, (1, mode), "f32")
+    _say(f"(1024,512) L=4 f32 mode={mode}, {b.F} frames")
     g = gpu_decode(code, 4, b.llr, "f32", mode=mode)
     o = oracle_decode(code, 4, b.llr, "f32", mode=mode)
-    exact = compare(g, o, "f32", "(1024,512)")
+    exact = compare(g, o, "f32", "(1024,512)", max_excused=b.F // 100)
     assert exact >= 0.99 * b.F
+    s = oracle.decode_scl(1024, 512, code.frozen, code.poly, 8, 4, b.llr, "f32")
     if mode == 1:
-        import oracle
-
-        s = oracle.decode_scl(1024, 512, code.frozen, code.poly, 8, 4, b.llr, "f32")
-        compare(g, s, "f32", "(1024,512) vs bit-by-bit SCL")
+        compare(g, s, "f32", "(1024,512) vs bit-by-bit SCL", max_excused=b.F // 100)
+    else:
+        k_g = int((g[0] != b.info).any(axis=1).sum())
+        k_s = int((s[0] != b.info).any(axis=1).sum())
+        lo_g, hi_g = _wilson(k_g, b.F)
+        lo_s, hi_s = _wilson(k_s, b.F)
+        _say(f"FER tree {k_g / b.F:.4f} [{lo_g:.4f}, {hi_g:.4f}], "
+             f"SC-list {k_s / b.F:.4f} [{lo_s:.4f}, {hi_s:.4f}]")
+        assert lo_g <= hi_s and lo_s <= hi_g
 
 
 @pytest.mark.parametrize("dtype", ["f32", "i8"])
