@@ -152,7 +152,7 @@ typedef struct {
      * where they are read instead of being stored, when they would live in
      * the workspace and only F / G / Combine touch their levels: 1 = none,
      * 2 = the stage of level n - 1, 3 = those of levels n - 1 and n - 2
-     * (0 = default: 2 for float32 and int16, 1 for int8). */
+     * (int8: as 2) (0 = default: 2 for float32 and int16, 1 for int8). */
     int recompute;
     /* float32 with L <= 32 only: forking leaves of at most 2^fuse_log2
      * values are scored, ranked and written in one wavefront (-1 = never,

@@ -616,8 +616,16 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     if (!q.valid) return;
     const int M = 1 << (k - 1);
     if constexpr (ISP == SP_VT) {
-        if (op_cand(op) & 8) pp_fg_virtual2<T, IS_G, OSP>(c, op, k, q);
-        else pp_fg_virtual<T, IS_G, OSP>(c, op, k, q);
+        // two recomputed levels are not offered for int8 (their eight
+        // clamped channel chunks per output chunk), so its kernels do not
+        // carry that code
+        if constexpr (!std::is_same<T, int8_t>::value) {
+            if (op_cand(op) & 8) {
+                pp_fg_virtual2<T, IS_G, OSP>(c, op, k, q);
+                return;
+            }
+        }
+        pp_fg_virtual<T, IS_G, OSP>(c, op, k, q);
         return;
     }
     const T* in = c.template in_stage<ISP>(op.x, k, ISP == SP_CH ? 0 : c.srcA(k, q.p));
@@ -1944,9 +1952,24 @@ struct WorkCounter {
     }
 };
 
+// Waves per SIMD the kernels are compiled for: five for int8, whose
+// default launch (64 threads, 8 KiB of LDS per frame) is otherwise limited
+// by registers to four resident frames per SIMD; four (up to 128 VGPRs) for
+// the others, which LDS limits first.
+template <typename T>
+struct WavesPerSimd {
+    static constexpr int value = 4;
+};
+template <>
+struct WavesPerSimd<int8_t> {
+    static constexpr int value = 5;
+};
+#define PSCL_KERNEL_BOUNDS(T) \
+    __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WavesPerSimd<T>::value)))
+
 // One code: frames taken from the counter, any workgroup any frame.
 template <typename T, bool WIDE>
-__global__ void __launch_bounds__(1024)
+__global__ void PSCL_KERNEL_BOUNDS(T)
     decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
                   uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                   void* __restrict__ pm_out, unsigned long long* __restrict__ counter) {
@@ -1987,7 +2010,7 @@ struct DevJob {
 // that frames of very different cost balance across workgroups; every
 // workgroup leaves once the counter has passed the last frame.
 template <typename T, bool WIDE>
-__global__ void __launch_bounds__(1024)
+__global__ void PSCL_KERNEL_BOUNDS(T)
     decode_mixed_kernel(const DevPlan* __restrict__ plans, const DevJob* __restrict__ jobs,
                         int n_jobs, int64_t total, const uint64_t* __restrict__ sched,
                         uint8_t* __restrict__ ws, int64_t ws_frame,
@@ -2087,7 +2110,7 @@ DEV int ring_wait(const pscl_ring::Args& r, uint64_t t) {
 }
 
 template <typename T, bool WIDE>
-__global__ void __launch_bounds__(1024)
+__global__ void PSCL_KERNEL_BOUNDS(T)
     serve_kernel(const DevPlan* __restrict__ plans, const uint64_t* __restrict__ sched,
                  uint8_t* __restrict__ ws, int64_t ws_frame, pscl_ring::Args r) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -2170,7 +2193,7 @@ __global__ void gather_failed(const uint8_t* __restrict__ crc_ok, int64_t F,
 
 // The gathered frames, each written back at its own index.
 template <typename T, bool WIDE>
-__global__ void __launch_bounds__(1024)
+__global__ void PSCL_KERNEL_BOUNDS(T)
     decode_gathered_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr,
                            const int64_t* __restrict__ idx,
                            const unsigned long long* __restrict__ count,
@@ -2485,7 +2508,9 @@ int virtual_depth(const pscl_plan* p, int k_glob) {
     // the stage must be wide enough for whole vector chunks
     const int V = 16 / elem_size(p->dtype);
     if (!only_fgc(n - 1) || (1 << (n - 2)) < V) return 0;
-    if (p->recompute >= 2 && n - 2 >= k_glob && only_fgc(n - 2) && (1 << (n - 3)) >= V) return 2;
+    if (p->recompute >= 2 && p->dtype != PSCL_I8 && n - 2 >= k_glob && only_fgc(n - 2) &&
+        (1 << (n - 3)) >= V)
+        return 2;
     return 1;
 }
 
