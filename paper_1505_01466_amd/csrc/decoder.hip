@@ -1952,10 +1952,12 @@ struct WorkCounter {
     }
 };
 
-// Waves per SIMD the kernels are compiled for: five for int8, whose
-// default launch (64 threads, 8 KiB of LDS per frame) is otherwise limited
-// by registers to four resident frames per SIMD; four (up to 128 VGPRs) for
-// the others, which LDS limits first.
+// Waves per SIMD the multi-code kernels are compiled for: five for int8,
+// whose default launch (64 threads, 8 KiB of LDS per frame) is otherwise
+// limited by registers to four resident frames per SIMD; four (up to 128
+// VGPRs) for the others, which LDS limits first.  The single-code kernel
+// fits five int8 waves without the bound, and is faster without it (the
+// bound makes the compiler trade registers for instructions).
 template <typename T>
 struct WavesPerSimd {
     static constexpr int value = 4;
@@ -1969,7 +1971,7 @@ struct WavesPerSimd<int8_t> {
 
 // One code: frames taken from the counter, any workgroup any frame.
 template <typename T, bool WIDE>
-__global__ void PSCL_KERNEL_BOUNDS(T)
+__global__ void __launch_bounds__(1024)
     decode_kernel(KArgs a, const uint64_t* __restrict__ sched, const T* __restrict__ llr, int64_t F,
                   uint8_t* __restrict__ u_hat, uint8_t* __restrict__ crc_ok,
                   void* __restrict__ pm_out, unsigned long long* __restrict__ counter) {
