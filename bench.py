@@ -294,8 +294,8 @@ def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), s
     """Poisson arrivals of requests of 1..64 frames of a random code of the
     mixed set (int8), replayed through a server launching batches on
     `streams` streams, through a persistent-mode server (one persistent
-    kernel consuming a request ring; with as many workgroups per CU as fit,
-    and with at most 4), and as plain per-request launches
+    kernel consuming a request ring, workgroups per CU taking frames adapted
+    to the load), and as plain per-request launches
     round-robin on `streams` streams (a set of plans per stream); p50 / p99
     latency (with order-statistic intervals) and sustained payload Gbps."""
     codes = c4_codes(synth)
@@ -317,12 +317,12 @@ def serving_leg(pk, torch, synth, np, rates=(10e3, 50e3, 100e3, 200e3, 500e3), s
         work = [(int(i), pool[int(i)][: int(f)]) for i, f in zip(idx, F)]
         bits = float(sum(payload[int(i)] * int(f) for i, f in zip(idx, F)))
         row = {"requests": n, "arrival_span_s": round(float(arrivals[-1]) * 1e-6, 4)}
-        for name in ("server", "persistent", "persistent_4_per_cu", "per_request"):
+        for name in ("server", "persistent", "per_request"):
             if name == "server":
                 sv = pk.Server(plans, streams=streams)
                 _, lat, el = pk.replay(plans, work, arrivals, server=sv)
-            elif name.startswith("persistent"):
-                sv = pk.Server(plans, persistent=True, wg_per_cu=4 if name.endswith("cu") else 0)
+            elif name == "persistent":
+                sv = pk.Server(plans, persistent=True)
                 _, lat, el = pk.replay(plans, work, arrivals, server=sv)
             else:
                 sv = None
@@ -402,10 +402,23 @@ def spc_plus_leg(pk, torch, synth, code, b, frames, dtype="f32", lists=(8, 32), 
 
 
 def fer_sweep_leg(pk, torch, code, frames_per_point, points=(3.5, 3.75, 4.0, 4.25, 4.5),
-                  dtypes=("f32", "i8"), chunk=65536, seed=0x46455253):
+                  dtypes=("f32", "i8"), chunk=65536, seed=0x46455253, jsonl=None):
     """Frame error rate of the L = 32 decoder over Eb/N0, with frames made on
     the device (Philox payloads and noise, see pscl_generate) chunk by chunk:
-    frame errors counted against the generated information bits."""
+    frame errors counted against the generated information bits.  With
+    jsonl (a path), every finished chunk appends one line (dtype, Eb/N0,
+    first frame, frames, errors, timings) and chunks already in the file are
+    not decoded again, so an interrupted sweep resumes where it stopped
+    (frame f is the same frame whatever run makes it)."""
+    done_chunks = {}
+    if jsonl and os.path.exists(jsonl):
+        with open(jsonl) as fh:
+            for line in fh:
+                line = line.strip()
+                if line:
+                    r = json.loads(line)
+                    done_chunks[(r["dtype"], r["ebn0_db"], r["first_frame"], r["frames"])] = r
+    log = open(jsonl, "a") if jsonl else None
     out = {}
     for dtype in dtypes:
         gen = pk.Generator(code.N, code.K, code.frozen, code.poly, code.r, dtype)
@@ -414,29 +427,46 @@ def fer_sweep_leg(pk, torch, code, frames_per_point, points=(3.5, 3.75, 4.0, 4.2
         u, ok, pm = plan.decode(llr)
         rows = {}
         gen_ms = dec_ms = 0.0
+        timed = 0
         for e in points:
             errs = 0
             done = 0
             while done < frames_per_point:
                 F = min(chunk, frames_per_point - done)
+                prev = done_chunks.get((dtype, e, done, F))
+                if prev is not None:
+                    errs += prev["errors"]
+                    done += F
+                    continue
                 e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
                 e0.record()
                 gen.generate(F, e, seed, first_frame=done, llr=llr[:F], info=info[:F])
                 e1.record()
                 plan.decode(llr[:F], u[:F], ok[:F], pm[:F])
                 e2.record()
-                errs += int((u[:F] != info[:F]).any(dim=1).sum().item())
-                gen_ms += e0.elapsed_time(e1)
-                dec_ms += e1.elapsed_time(e2)
+                k = int((u[:F] != info[:F]).any(dim=1).sum().item())
+                errs += k
+                g_ms, d_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+                gen_ms += g_ms
+                dec_ms += d_ms
+                timed += F
+                if log:
+                    log.write(json.dumps({"dtype": dtype, "ebn0_db": e, "first_frame": done,
+                                          "frames": F, "errors": k, "seed": seed,
+                                          "gen_ms": round(g_ms, 4), "dec_ms": round(d_ms, 4)})
+                              + "\n")
+                    log.flush()
                 done += F
             lo, hi = wilson(errs, done)
             rows[str(e)] = {"frames": done, "errors": errs, "fer": errs / done,
                             "ci95": [round(lo, 8), round(hi, 8)]}
-        n_all = frames_per_point * len(points)
-        out[dtype] = {"points": rows, "generator_frames_per_s": round(n_all / (gen_ms * 1e-3)),
-                      "decoder_frames_per_s": round(n_all / (dec_ms * 1e-3))}
+        out[dtype] = {"points": rows,
+                      "generator_frames_per_s": round(timed / (gen_ms * 1e-3)) if gen_ms else None,
+                      "decoder_frames_per_s": round(timed / (dec_ms * 1e-3)) if dec_ms else None}
         gen.close()
         plan.close()
+    if log:
+        log.close()
     return out
 
 
@@ -648,6 +678,9 @@ def main():
                     help="frames per Eb/N0 point of the CRC-length study")
     ap.add_argument("--sweep-frames", type=int, default=1 << 20,
                     help="frames per Eb/N0 point of the FER sweep (made on the device)")
+    ap.add_argument("--sweep-jsonl", default=None,
+                    help="append each FER-sweep chunk to this JSONL file and skip the chunks "
+                         "it already holds (resumable sweeps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -794,7 +827,7 @@ def main():
     if not args.single and not args.no_fer_sweep:
         print(f"[bench] FER sweep, {args.sweep_frames} device-made frames per point",
               file=sys.stderr, flush=True)
-        sweep = fer_sweep_leg(pk, torch, code, args.sweep_frames)
+        sweep = fer_sweep_leg(pk, torch, code, args.sweep_frames, jsonl=args.sweep_jsonl)
     if not args.single and not args.no_spc_plus:
         print("[bench] SPC-4 vs SPC-4+", file=sys.stderr, flush=True)
         spc_plus = spc_plus_leg(pk, torch, synth, code, b, args.frames)

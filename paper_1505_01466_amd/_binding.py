@@ -62,7 +62,7 @@ class ServerCfg(ctypes.Structure):
                 ("max_pending_frames", ctypes.c_int64), ("max_batch_frames", ctypes.c_int64),
                 ("max_batch_requests", ctypes.c_int), ("max_footprint_bytes", ctypes.c_int64),
                 ("persistent", ctypes.c_int), ("idle_us", ctypes.c_int),
-                ("wg_per_cu", ctypes.c_int)]
+                ("wg_per_cu", ctypes.c_int), ("active_per_cu", ctypes.c_int)]
 
 
 def _load():
@@ -407,12 +407,13 @@ class Server:
     def __init__(self, plans, streams: int = 2, max_requests: int = 0,
                  max_pending_frames: int = 0, max_batch_frames: int = 0,
                  max_batch_requests: int = 0, max_footprint_bytes: int = 0,
-                 persistent: bool = False, idle_us: int = 0, wg_per_cu: int = 0):
+                 persistent: bool = False, idle_us: int = 0, wg_per_cu: int = 0,
+                 active_per_cu: int = 0):
         self.plans = list(plans)
         self._hs = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         cfg = ServerCfg(self._hs, len(self.plans), streams, max_requests, max_pending_frames,
                         max_batch_frames, max_batch_requests, max_footprint_bytes,
-                        1 if persistent else 0, idle_us, wg_per_cu)
+                        1 if persistent else 0, idle_us, wg_per_cu, active_per_cu)
         h = ctypes.c_void_p(None)
         _check(lib.pscl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pscl_server_create")
         self._h = h

@@ -2059,6 +2059,63 @@ DEV uint32_t ld_sys(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Reads the host's published count, stop flag and active workgroups per CU
+// into their device copies, if no other workgroup is doing so; returns the
+// published count (or pub when another workgroup holds the lease).
+DEV unsigned long long ring_refresh(const pscl_ring::Args& r, unsigned long long pub) {
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    pscl_ring::Dev* dv = r.dev;
+    if (__hip_atomic_load(&dv->lease, __ATOMIC_RELAXED, AG) != 0u ||
+        __hip_atomic_exchange(&dv->lease, 1u, __ATOMIC_ACQUIRE, AG) != 0u)
+        return pub;
+    const uint64_t hp =
+        __hip_atomic_load(&r.ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (ld_sys(&r.ctl->stop)) __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELAXED, AG);
+    __hip_atomic_store(&dv->active, ld_sys(&r.ctl->active), __ATOMIC_RELAXED, AG);
+    __hip_atomic_fetch_max(&dv->published, (unsigned long long)hp, __ATOMIC_RELEASE, AG);
+    __hip_atomic_store(&dv->lease, 0u, __ATOMIC_RELEASE, AG);
+    return hp > pub ? hp : pub;
+}
+
+// Waits until this workgroup's rank among those started on its CU is below
+// the active count: 1 then, 0 when the host has raised stop or nothing new
+// was published for idle_us (as ring_wait).  Waiting workgroups only read
+// the device copies (the workgroups waiting for a ticket refresh them), and
+// poll every ~55 us.
+DEV int ring_admit(const pscl_ring::Args& r, uint32_t rank) {
+    constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
+    pscl_ring::Dev* dv = r.dev;
+    // the first workgroup of every CU always takes frames (and, waiting for
+    // tickets, refreshes the device copies, `active` among them)
+    if (rank == 0 || rank < __hip_atomic_load(&dv->active, __ATOMIC_RELAXED, AG)) return 1;
+    uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    const uint64_t idle = (uint64_t)r.idle_us * 100u;
+    const uint32_t max_polls = r.idle_us / 16u + 64u;
+    unsigned long long last = __hip_atomic_load(&dv->published, __ATOMIC_RELAXED, AG);
+    for (uint32_t poll = 0;; ++poll) {
+        for (int i = 0; i < 16; ++i) __builtin_amdgcn_s_sleep(127);
+        if (rank < __hip_atomic_load(&dv->active, __ATOMIC_RELAXED, AG)) return 1;
+        if (__hip_atomic_load(&dv->stop, __ATOMIC_RELAXED, AG)) return 0;
+        const unsigned long long now = __hip_atomic_load(&dv->published, __ATOMIC_RELAXED, AG);
+        if (now != last) {  // progress: the idle clock restarts
+            last = now;
+            t0 = __builtin_amdgcn_s_memrealtime();
+            poll = 0;
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > idle || poll >= max_polls) return 0;
+    }
+}
+
+// The compute unit this wave runs on, as an index below kCuSlots: the XCC
+// (HW_REG_XCC_ID) and the shader engine, shader array and CU fields of
+// HW_REG_HW_ID.
+DEV uint32_t cu_slot() {
+    const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID
+    const uint32_t cu = (hw >> 8) & 0xfu, sh = (hw >> 12) & 1u, se = (hw >> 13) & 7u;
+    return ((xcc & 7u) << 8) | (se << 5) | (sh << 4) | cu;
+}
+
 // A ticket: the next frame left unclaimed by the previous launch, else a
 // new frame number.
 DEV int64_t ring_ticket(const pscl_ring::Args& r) {
@@ -2087,15 +2144,7 @@ DEV int ring_wait(const pscl_ring::Args& r, uint64_t t) {
     unsigned long long last = __hip_atomic_load(&dv->published, __ATOMIC_ACQUIRE, AG);
     for (uint32_t poll = 0;; ++poll) {
         unsigned long long pub = __hip_atomic_load(&dv->published, __ATOMIC_ACQUIRE, AG);
-        if (pub <= t && __hip_atomic_load(&dv->lease, __ATOMIC_RELAXED, AG) == 0u &&
-            __hip_atomic_exchange(&dv->lease, 1u, __ATOMIC_ACQUIRE, AG) == 0u) {
-            const uint64_t hp =
-                __hip_atomic_load(&r.ctl->published, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (ld_sys(&r.ctl->stop)) __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELAXED, AG);
-            __hip_atomic_fetch_max(&dv->published, (unsigned long long)hp, __ATOMIC_RELEASE, AG);
-            __hip_atomic_store(&dv->lease, 0u, __ATOMIC_RELEASE, AG);
-            pub = hp > pub ? hp : pub;
-        }
+        if (pub <= t) pub = ring_refresh(r, pub);
         if (pub > t) return 1;
         if (__hip_atomic_load(&dv->stop, __ATOMIC_RELAXED, AG)) return 0;
         if (pub != last) {  // progress: the idle clock restarts
@@ -2124,22 +2173,32 @@ __global__ void PSCL_KERNEL_BOUNDS(T)
     c.NT = blockDim.x;
     c.lane = threadIdx.x & 63;
     uint8_t* wsb = ws + (int64_t)blockIdx.x * ws_frame;
+    // this workgroup's rank among those started on its CU
+    uint32_t rank = 0;
+    if (c.tid == 0)
+        rank = __hip_atomic_fetch_add(r.cu_rank + cu_slot(), 1u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if (c.tid == 0) {
-            const int64_t t = ring_ticket(r);
-            int64_t g = t;
-            if (!ring_wait(r, (uint64_t)t)) {
+            int64_t g = -1;
+            if (ring_admit(r, rank)) {
+                const int64_t t = ring_ticket(r);
+                g = t;
+                if (!ring_wait(r, (uint64_t)t)) {
                 // leaving with an unpublished frame: the next launch takes it
                 const uint32_t k = __hip_atomic_fetch_add(&r.dev->orphan_n[r.parity], 1u,
                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                r.orphans[(uint64_t)r.parity * r.orphan_cap + k] = (unsigned long long)t;
-                g = -1;
+                    r.orphans[(uint64_t)r.parity * r.orphan_cap + k] = (unsigned long long)t;
+                    g = -1;
+                }
             }
             slot = g;
         }
         __syncthreads();
         const int64_t g = slot;
         if (g < 0) break;
+        // inputs may have been written since this CU last cached them
+        if (c.tid == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         // the frame's record: eight words read from host memory by eight
         // lanes in one load
         static_assert(sizeof(pscl_ring::Rec) == 8 * sizeof(uint64_t), "record of eight words");
@@ -2152,15 +2211,15 @@ __global__ void PSCL_KERNEL_BOUNDS(T)
         const KArgs a = D.a;
         bind_plan(c, a, wsb);
         c.chan = (const T*)d.llr;
-        decode_frame<T, WIDE>(c, a, sched + D.op_base, 0, d.u_hat, d.crc_ok, d.pm);
-        // every thread's outputs of the frame written back and visible to
-        // the host and other agents before the count
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        // outputs written through the L2 at system scope (no write-back of
+        // the whole cache per frame), complete before the count
+        decode_frame<T, WIDE, true>(c, a, sched + D.op_base, 0, d.u_hat, d.crc_ok, d.pm);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (c.tid == 0) {
             const uint32_t s = d.slot;
             const uint32_t prev =
-                __hip_atomic_fetch_add(r.count + s, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(r.count + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((int64_t)prev + 1 == d.F) {
                 // the request's last frame: reset the slot's count, then
                 // report the ticket
@@ -3371,7 +3430,7 @@ pscl_status pscl_group_decode(pscl_group* g, const pscl_job* jobs, int n_jobs, v
 // workgroups as the kernel can keep resident, at most the group's grid (the
 // group's first workspace has that many slots).
 pscl_status pscl_ring::launch(pscl_group* g, const pscl_ring::Args& r, hipStream_t s) {
-    if (!g || !r.ctl || !r.rec || !r.done || !r.count || !r.dev || !r.orphans)
+    if (!g || !r.ctl || !r.rec || !r.done || !r.count || !r.dev || !r.orphans || !r.cu_rank)
         return PSCL_E_INVALID;
     const void* kern = g->wide ? serve_kernel_for<true>(g->dtype) : serve_kernel_for<false>(g->dtype);
     pscl_status st = hip_status(
@@ -3385,13 +3444,16 @@ pscl_status pscl_ring::launch(pscl_group* g, const pscl_ring::Args& r, hipStream
     if (occ < 1) return PSCL_E_UNSUPPORTED;
     if (r.wg_per_cu > 0) occ = std::min(occ, (int)r.wg_per_cu);
     const int grid = std::min<int>(std::min(g->grid, occ * cus), (int)r.orphan_cap);
+    pscl_ring::Args ra = r;
+    ra.cus = (uint32_t)cus;
     // this launch's orphan list and the previous one's take count start at 0
     pscl_ring::Dev* dv = r.dev;
     if (hipMemsetAsync(&dv->orphan_n[r.parity], 0, 4, s) != hipSuccess ||
-        hipMemsetAsync(&dv->orphan_take[r.parity ^ 1u], 0, 4, s) != hipSuccess)
+        hipMemsetAsync(&dv->orphan_take[r.parity ^ 1u], 0, 4, s) != hipSuccess ||
+        hipMemsetAsync(r.cu_rank, 0, sizeof(uint32_t) * pscl_ring::kCuSlots, s) != hipSuccess)
         return PSCL_E_HIP;
-    if (g->wide) launch_serve<true>(g, grid, r, s);
-    else launch_serve<false>(g, grid, r, s);
+    if (g->wide) launch_serve<true>(g, grid, ra, s);
+    else launch_serve<false>(g, grid, ra, s);
     return hip_status(hipGetLastError());
 }
 

@@ -40,7 +40,7 @@ static_assert(sizeof(Rec) == 64, "a frame record is eight 8-byte words");
 struct Ctl {
     uint64_t published;  // frames published so far
     uint32_t stop;       // 1: every workgroup leaves at its next claim
-    uint32_t pad;
+    uint32_t active;     // workgroups per CU that take frames (by launch rank)
 };
 
 // Device-side state.  A free workgroup takes a ticket, the number of the
@@ -53,13 +53,16 @@ struct Ctl {
 // frame records it in the orphan list of its launch's parity (at most one
 // per workgroup); the next launch takes those tickets first.  The host
 // clears orphan_n[p] and orphan_take[1 - p] before a launch of parity p.
+// Each group of words that different workgroups poll or update sits in a
+// cache line of its own.
 struct Dev {
-    unsigned long long next;       // next new ticket
-    unsigned long long published;  // latest published count seen
-    uint32_t lease;                // 1 while a workgroup reads host memory
-    uint32_t stop;
-    uint32_t orphan_n[2];     // tickets left by the launch of each parity
-    uint32_t orphan_take[2];  // of those, taken by the next launch
+    alignas(128) unsigned long long next;  // next new ticket
+    alignas(128) unsigned long long published;  // latest published count seen
+    alignas(128) uint32_t lease;           // 1 while a workgroup reads host memory
+    alignas(128) uint32_t stop;
+    uint32_t active;                       // latest `active` seen
+    alignas(128) uint32_t orphan_n[2];     // tickets left by the launch of each parity
+    uint32_t orphan_take[2];               // of those, taken by the next launch
 };
 
 struct Args {
@@ -74,7 +77,13 @@ struct Args {
     uint32_t rec_mask;
     uint32_t idle_us;
     uint32_t wg_per_cu;  // resident workgroups per CU at most (0: as many as fit)
+    uint32_t cus;        // compute units (set by launch)
+    uint32_t* cu_rank;   // device, kCuSlots counters: workgroups started per CU
 };
+
+// Counters of workgroups per compute unit, indexed by the unit's hardware
+// identity (XCC, shader engine, shader array, CU).
+constexpr int kCuSlots = 2048;
 
 // Launches the persistent serving kernel for the plans of group g (its
 // concatenated schedules, plan table, first workspace, grid and LDS) on

@@ -96,12 +96,16 @@ struct pscl_server {
     uint32_t* rcount = nullptr;
     pscl_ring::Dev* rdev = nullptr;
     unsigned long long* rorphans = nullptr;
+    uint32_t* rcu = nullptr;
     pscl_ring::Args rargs{};
     int64_t rec_size = 0;
     std::vector<int64_t> row_in, row_out;  // LLR row bytes and K per plan
     int64_t ring_frames = 0;  // published and not finished
     uint64_t published = 0;
     uint32_t idle_us = 2000;
+    int cus = 1;
+    int active_cfg = 0;      // fixed workgroups per CU taking frames (0: adaptive)
+    uint32_t active_set = 0;  // value last written to the ring
     std::vector<int> free_slots;
     std::vector<Req> slot_req;
     std::vector<int> busy_slots;
@@ -271,6 +275,17 @@ void pscl_server::run_ring() {
                 progress = true;
             }
         }
+        // workgroups per CU taking frames: at least four, and as many as the
+        // frames outstanding per CU (all, under load)
+        {
+            const int64_t per_cu = (ring_frames + cus - 1) / cus;
+            const uint32_t want = active_cfg > 0 ? (uint32_t)active_cfg
+                                                 : (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(4, per_cu));
+            if (want != active_set) {
+                __atomic_store_n(&ctl->active, want, __ATOMIC_RELEASE);
+                active_set = want;
+            }
+        }
         // a launch while requests are held
         if (!busy_slots.empty()) {
             bool running = rlaunched && hipEventQuery(rev) == hipErrorNotReady;
@@ -394,7 +409,8 @@ static pscl_status ring_setup(pscl_server* sv, const pscl_server_cfg* cfg) {
         return PSCL_E_NOMEM;
     // orphan lists: at most one ticket per workgroup per launch
     const uint32_t cap = 1u << 16;
-    if (hipMalloc((void**)&sv->rorphans, sizeof(unsigned long long) * 2 * cap) != hipSuccess)
+    if (hipMalloc((void**)&sv->rorphans, sizeof(unsigned long long) * 2 * cap) != hipSuccess ||
+        hipMalloc((void**)&sv->rcu, sizeof(uint32_t) * pscl_ring::kCuSlots) != hipSuccess)
         return PSCL_E_NOMEM;
     if (hipMemset(sv->rcount, 0, sizeof(uint32_t) * (size_t)R) != hipSuccess ||
         hipMemset(sv->rdev, 0, sizeof(pscl_ring::Dev)) != hipSuccess ||
@@ -414,11 +430,17 @@ static pscl_status ring_setup(pscl_server* sv, const pscl_server_cfg* cfg) {
     a.count = sv->rcount;
     a.dev = sv->rdev;
     a.orphans = sv->rorphans;
+    a.cu_rank = sv->rcu;
     a.orphan_cap = cap;
     a.parity = 0;
     a.rec_mask = (uint32_t)(sv->rec_size - 1);
     a.idle_us = sv->idle_us;
     a.wg_per_cu = (uint32_t)cfg->wg_per_cu;
+    a.cus = 1;  // set by each launch
+    sv->active_cfg = cfg->active_per_cu;
+    if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess ||
+        sv->cus < 1)
+        return PSCL_E_HIP;
     sv->slot_req.resize((size_t)R);
     for (int i = R - 1; i >= 0; --i) sv->free_slots.push_back(i);
     return st;
@@ -447,6 +469,7 @@ void pscl_server_destroy(pscl_server* sv) {
     (void)hipFree(sv->rcount);
     (void)hipFree(sv->rdev);
     (void)hipFree(sv->rorphans);
+    (void)hipFree(sv->rcu);
     for (pscl_group* g : sv->groups) pscl_group_destroy(g);
     for (hipEvent_t e : sv->ev)
         if (e) (void)hipEventDestroy(e);
@@ -461,7 +484,7 @@ pscl_status pscl_server_create(const pscl_server_cfg* cfg, pscl_server** out) {
     if (cfg->streams < 0 || cfg->streams > 8 || cfg->max_requests < 0 ||
         cfg->max_pending_frames < 0 || cfg->max_batch_frames < 0 || cfg->max_batch_requests < 0 ||
         cfg->max_footprint_bytes < 0 || cfg->persistent < 0 || cfg->persistent > 1 ||
-        cfg->idle_us < 0 || cfg->wg_per_cu < 0)
+        cfg->idle_us < 0 || cfg->wg_per_cu < 0 || cfg->active_per_cu < 0)
         return PSCL_E_INVALID;
     for (int i = 0; i < cfg->n_plans; ++i)
         if (!cfg->plans[i]) return PSCL_E_INVALID;

@@ -100,3 +100,38 @@ def test_decoder_recovers_generated_frames(pk, dtype):
     assert bool(ok.all())
     assert torch.equal(u, info)
     g.close()
+
+
+def test_resumable_fer_sweep(tmp_path):
+    """bench's FER sweep with a JSONL log: an interrupted sweep (the log
+    truncated to its first chunks) resumes, decodes only the missing chunks
+    and reaches the same frame-error counts as an uninterrupted one."""
+    import json
+    import os
+    import sys
+
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    import paper_1505_01466_amd as pk
+
+    code = synth.make_code(256, 128, 8, synth.CRC8_POLY, 2.5)
+    path = str(tmp_path / "sweep.jsonl")
+    kw = dict(points=(1.5, 2.0), dtypes=("i8",), chunk=4096)
+    full = bench.fer_sweep_leg(pk, torch, code, 20000, jsonl=path, **kw)
+    lines = open(path).read().splitlines()
+    assert len(lines) == 2 * 5  # 5 chunks per point
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines[:3]) + "\n")
+    again = bench.fer_sweep_leg(pk, torch, code, 20000, jsonl=path, **kw)
+    assert len(open(path).read().splitlines()) == 10
+    for e in ("1.5", "2.0"):
+        assert again["i8"]["points"][e]["errors"] == full["i8"]["points"][e]["errors"]
+        assert again["i8"]["points"][e]["frames"] == 20000
+    assert full["i8"]["points"]["1.5"]["errors"] > 0
+    # every recorded chunk once
+    keys = [(r["ebn0_db"], r["first_frame"]) for r in map(json.loads, open(path))]
+    assert len(set(keys)) == 10
