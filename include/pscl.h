@@ -158,6 +158,12 @@ typedef struct {
      * values are scored, ranked and written in one wavefront (-1 = never,
      * 1..5; 0 = default 5); ignored otherwise. */
     int fuse_log2;
+    /* Tree levels one F / G pass descends (the unrolling of Sec. II-D at
+     * the granularity of node operations): 1 = each F and G its own pass;
+     * 2 = an F or G immediately followed by the F of its left child runs as
+     * one pass that stores both outputs without re-reading the first
+     * (0 = default 2). */
+    int unroll;
 } pscl_launch_cfg;
 
 /* pscl_plan_create with an explicit launch shape (cfg may be NULL).
@@ -175,8 +181,8 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
  * once: waves per frame (threads 64, 128, 256) x LDS budget (8 to 48 KiB:
  * which tree levels stay on chip); then the stages recomputed below the
  * root (recompute 1..3); then, for float32 with L <= 32, the largest fused
- * forking leaf (fuse_log2 -1, 3, 4, 5); then a residency cap (2, 4, 8
- * workgroups per CU).  Allocates and frees plans and output buffers while
+ * forking leaf (fuse_log2 -1, 3, 4, 5); then the tree levels per F / G
+ * pass (unroll 1, 2); then a residency cap (2, 4, 8 workgroups per CU).  Allocates and frees plans and output buffers while
  * it runs, so it belongs to set-up, not to a decoding loop.  Same argument
  * rules and errors as pscl_plan_create.
  */
@@ -299,7 +305,8 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
  * launch configuration at a time, searched coordinate by coordinate: group
  * threads (64, 128, 256) x LDS budget per plan (8 to 32 KiB); then the
  * stages recomputed below the root (recompute 1..3); then, for float32, the
- * largest fused forking leaf (fuse_log2 -1, 4, 5).  Writes the fastest
+ * largest fused forking leaf (fuse_log2 -1, 4, 5); then the tree levels per
+ * F / G pass (unroll 1, 2).  Writes the fastest
  * configuration for each plan to cfgs[0 .. n_plans) (pass each to
  * pscl_plan_create_cfg), the group's threads to *threads (pass them to
  * pscl_group_create) and the time per call in milliseconds to *best_ms

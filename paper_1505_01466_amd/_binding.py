@@ -44,7 +44,7 @@ class LaunchCfg(ctypes.Structure):
 
     _fields_ = [("threads", ctypes.c_int), ("lds_budget", ctypes.c_int),
                 ("max_wg_per_cu", ctypes.c_int), ("recompute", ctypes.c_int),
-                ("fuse_log2", ctypes.c_int)]
+                ("fuse_log2", ctypes.c_int), ("unroll", ctypes.c_int)]
 
 
 class Job(ctypes.Structure):
@@ -194,7 +194,8 @@ class Plan:
     def __init__(self, N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int,
                  dtype: str = "f32", spc_max: int = 4, mode: int = MODE_TREE,
                  threads: int = 0, lds_budget: int = 0, max_wg_per_cu: int = 0,
-                 recompute: int = 0, fuse_log2: int = 0, cfg: dict | None = None):
+                 recompute: int = 0, fuse_log2: int = 0, unroll: int = 0,
+                 cfg: dict | None = None):
         import torch
 
         if dtype not in DTYPES:
@@ -208,9 +209,10 @@ class Plan:
             threads, lds_budget = cfg.get("threads", 0), cfg.get("lds_budget", 0)
             max_wg_per_cu = cfg.get("max_wg_per_cu", 0)
             recompute, fuse_log2 = cfg.get("recompute", 0), cfg.get("fuse_log2", 0)
+            unroll = cfg.get("unroll", 0)
         self.cfg = {"threads": threads, "lds_budget": lds_budget, "max_wg_per_cu": max_wg_per_cu,
-                    "recompute": recompute, "fuse_log2": fuse_log2}
-        cfg = LaunchCfg(threads, lds_budget, max_wg_per_cu, recompute, fuse_log2)
+                    "recompute": recompute, "fuse_log2": fuse_log2, "unroll": unroll}
+        cfg = LaunchCfg(threads, lds_budget, max_wg_per_cu, recompute, fuse_log2, unroll)
         _check(lib.pscl_plan_create_cfg(N, K, _u8p(fz), crc_poly, crc_len, L, DTYPES[dtype],
                                         spc_max, mode, ctypes.byref(cfg), ctypes.byref(h)),
                "pscl_plan_create_cfg")
@@ -312,7 +314,7 @@ def autotune(N: int, K: int, frozen, crc_poly: int, crc_len: int, L: int, llr,
                              ctypes.byref(best), ctypes.byref(ms)), "pscl_autotune")
     return ({"threads": best.threads, "lds_budget": best.lds_budget,
              "max_wg_per_cu": best.max_wg_per_cu, "recompute": best.recompute,
-             "fuse_log2": best.fuse_log2}, ms.value)
+             "fuse_log2": best.fuse_log2, "unroll": best.unroll}, ms.value)
 
 
 def _jobs(plans, work):
@@ -351,7 +353,7 @@ def autotune_group(plans, work):
     _check(lib.pscl_autotune_group(hs, len(plans), arr, len(work), _stream_handle(plans[0].device),
                                    cfgs, ctypes.byref(t), ctypes.byref(ms)), "pscl_autotune_group")
     out = [{"threads": c.threads, "lds_budget": c.lds_budget, "max_wg_per_cu": c.max_wg_per_cu,
-            "recompute": c.recompute, "fuse_log2": c.fuse_log2} for c in cfgs]
+            "recompute": c.recompute, "fuse_log2": c.fuse_log2, "unroll": c.unroll} for c in cfgs]
     return out, t.value, ms.value
 
 

@@ -684,6 +684,86 @@ DEV void pp_fg(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     if (q.g == 0) c.setA(k - 1, q.p);
 }
 
+// F or G at a level-k node followed at once by the F of its left child
+// (two tree levels in one pass; the child's record then does nothing): lane
+// g of the group takes output chunks g, g + G, ... of the child's F, forms
+// for each the two chunks of the node's output that this F combines from
+// four input chunks, stores both (the child's G reads them later) and stores
+// the F's chunk.  The child's input is never re-read.  Same arithmetic, in
+// the same order, as the two operations.
+template <typename T, bool IS_G, int ISP, int OSP1, int OSP2>
+DEV void pp_fg_chain(const Ctx<T>& c, const OpRec& op, int y2, int k, const Grp& q) {
+    using IO = VecIO<T>;
+    using CF = ChunkFG<T>;
+    constexpr int LOGV = IO::LOGV;
+    // int8 (one wavefront per frame, five per SIMD) keeps its registers
+    // within that budget with one chunk in flight
+    constexpr int U = sizeof(T) == 1 ? 1 : 2;
+    if (!q.valid) return;
+    const int M = 1 << (k - 1);  // the node's outputs
+    const int H = M >> 1;        // the child's F outputs
+    const T* in = c.template stage<ISP>(op.x, k, c.srcA(k, q.p));
+    T* mid = c.template stage<OSP1>(op.y, k - 1, q.p);
+    T* out = c.template stage<OSP2>(y2, k - 2, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.template bw<OSP1>(op.z, k - 1, c.srcB(k - 1, q.p));
+    const int nch = H >> LOGV;
+    for (int ch0 = q.g; ch0 < nch; ch0 += q.G * U) {
+        uint4 a0[U], a1[U], b0[U], b1[U];
+        uint32_t s0[U], s1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ch = ch0 + u * q.G;
+            const int e = (ch < nch ? ch : ch0) << LOGV;
+            a0[u] = *(const uint4*)(in + e);
+            a1[u] = *(const uint4*)(in + M + e);
+            b0[u] = *(const uint4*)(in + H + e);
+            b1[u] = *(const uint4*)(in + M + H + e);
+            if constexpr (IS_G) {
+                s0[u] = bl[e >> 5] >> (e & 31);
+                s1[u] = bl[(H + e) >> 5] >> ((H + e) & 31);
+            } else {
+                s0[u] = s1[u] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int ch = ch0 + u * q.G;
+            if (ch >= nch) continue;
+            const int e = ch << LOGV;
+            uint4 x, y;
+            if constexpr (IS_G) {
+                x = CF::g(a0[u], a1[u], s0[u]);
+                y = CF::g(b0[u], b1[u], s1[u]);
+            } else {
+                x = CF::f(a0[u], a1[u]);
+                y = CF::f(b0[u], b1[u]);
+            }
+            *(uint4*)(mid + e) = x;
+            *(uint4*)(mid + H + e) = y;
+            *(uint4*)(out + e) = CF::f(x, y);
+        }
+    }
+    if (q.g == 0) {
+        c.setA(k - 1, q.p);
+        c.setA(k - 2, q.p);
+    }
+}
+
+// The chained form's spaces: input, node output and child output, each in
+// LDS or the workspace, a level in LDS only if every level below it is.
+template <typename T, bool IS_G>
+DEV void pp_fg_chain_any(const Ctx<T>& c, const OpRec& op, uint64_t next, int k, const Grp& q) {
+    const int isp = op_isp(op);
+    const int osp = op_osp(op);
+    const int y2 = (int)(uint16_t)(next >> 32);
+    const int osp2 = ((int)(uint16_t)next >> 14) & 3;
+    if (isp == SP_LDS) pp_fg_chain<T, IS_G, SP_LDS, SP_LDS, SP_LDS>(c, op, y2, k, q);
+    else if (osp == SP_LDS) pp_fg_chain<T, IS_G, SP_WS, SP_LDS, SP_LDS>(c, op, y2, k, q);
+    else if (osp2 == SP_LDS) pp_fg_chain<T, IS_G, SP_WS, SP_WS, SP_LDS>(c, op, y2, k, q);
+    else pp_fg_chain<T, IS_G, SP_WS, SP_WS, SP_WS>(c, op, y2, k, q);
+}
+
 template <typename T, bool IS_G>
 DEV void pp_fg_any(const Ctx<T>& c, const OpRec& op, int k, const Grp& q) {
     const int isp = op_isp(op);
@@ -1880,10 +1960,12 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
         }
         switch (type) {
             case OP_F:
-                pp_fg_any<T, false>(c, op, k, q);
+                if (cc & 4) pp_fg_chain_any<T, false>(c, op, nraw, k, q);
+                else pp_fg_any<T, false>(c, op, k, q);
                 break;
             case OP_G:
-                pp_fg_any<T, true>(c, op, k, q);
+                if (cc & 4) pp_fg_chain_any<T, true>(c, op, nraw, k, q);
+                else pp_fg_any<T, true>(c, op, k, q);
                 break;
             case OP_COMB:
                 pp_comb_any<T>(c, op, k, side, q);
@@ -2314,6 +2396,7 @@ struct pscl_plan {
     int NT = 128, grid_max = 0, lds_bytes = 0, k_glob = 0;
     int recompute = 0;  // stages below the root recomputed at most (0..2)
     int fuse_k = -1;    // float32 fused forks up to 2^fuse_k values (-1: none)
+    int chain = 0;      // F / G chained with the left child's F when it follows (0 / 1)
     const void* kernel = nullptr;
     std::vector<uint8_t> frozen;
 };
@@ -2635,6 +2718,31 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
                             ((uint32_t)s.cand << 8) | ((uint32_t)isp << 12) | ((uint32_t)osp << 14));
         out.push_back(r);
     }
+    if (p->chain > 0) {
+        // an F / G whose output the next record's F reads at once: both run
+        // as one chained pass (candidate bit 2 of the first; the second
+        // becomes a no-op keeping its output offset and space), where the
+        // child's F output is at least one vector chunk
+        const int V = 16 / elem_size(p->dtype);
+        auto f_type = [](const OpRec& r) { return (int)(r.meta & 7); };
+        auto f_k = [](const OpRec& r) { return (int)((r.meta >> 3) & 15); };
+        auto f_isp = [](const OpRec& r) { return (int)((r.meta >> 12) & 3); };
+        auto f_osp = [](const OpRec& r) { return (int)((r.meta >> 14) & 3); };
+        for (size_t i = 0; i + 1 < out.size(); ++i) {
+            OpRec& a = out[i];
+            OpRec& b = out[i + 1];
+            const int ta = f_type(a), ka = f_k(a), ia = f_isp(a);
+            if (ta != OP_F && ta != OP_G) continue;
+            if (ia != SP_LDS && ia != SP_WS) continue;
+            if (((a.meta >> 8) & 15) != 0) continue;
+            if (f_type(b) != OP_F || f_k(b) != ka - 1 || f_isp(b) != f_osp(a) || b.x != a.y)
+                continue;
+            if (ka < 2 || (1 << (ka - 2)) < V) continue;
+            a.meta = (uint16_t)(a.meta | (4u << 8));
+            b.meta = (uint16_t)(OP_NOP | ((uint32_t)f_osp(b) << 14));
+            ++i;
+        }
+    }
     return out;
 }
 
@@ -2673,10 +2781,13 @@ static void drop_cached_groups(const pscl_plan* p) {
 // traffic saved), and recomputing two levels costs more than it saves in
 // every dtype; fusing forking leaves of up to 32 values in one wavefront
 // pays for float32 (two wavefronts per frame) and not for the integer
-// dtypes (one), whose kernels do not carry the fused form.
-static void default_layout(int dtype, int L, int& recompute, int& fuse_k) {
+// dtypes (one), whose kernels do not carry the fused form; chaining an F / G
+// with its left child's F pays in every dtype (float32 +5 %, int16 +3 %,
+// int8 +2 %).
+static void default_layout(int dtype, int L, int& recompute, int& fuse_k, int& chain) {
     recompute = dtype == PSCL_I8 ? 0 : 1;
     fuse_k = (dtype == PSCL_F32 && L <= 32) ? 5 : -1;
+    chain = 1;
 }
 
 static void default_launch(int dtype, int L, int& threads, int& budget, int& wg_cap) {
@@ -2830,8 +2941,12 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     if (cfg && cfg->max_wg_per_cu) wg_cap = cfg->max_wg_per_cu;
     if (NT != 64 && NT != 128 && NT != 256 && NT != 512 && NT != 1024) return PSCL_E_INVALID;
     if (budget < 0 || wg_cap < 0) return PSCL_E_INVALID;
-    int recompute = 0, fuse_k = -1;
-    default_layout(dtype, L, recompute, fuse_k);
+    int recompute = 0, fuse_k = -1, chain = 0;
+    default_layout(dtype, L, recompute, fuse_k, chain);
+    if (cfg && cfg->unroll) {
+        if (cfg->unroll < 1 || cfg->unroll > 2) return PSCL_E_INVALID;
+        chain = cfg->unroll - 1;
+    }
     if (cfg && cfg->recompute) {
         if (cfg->recompute < 1 || cfg->recompute > 3) return PSCL_E_INVALID;
         recompute = cfg->recompute - 1;
@@ -2866,6 +2981,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     p->frozen.assign(frozen_mask, frozen_mask + N);
     p->recompute = recompute;
     p->fuse_k = fuse_k;
+    p->chain = chain;
     while ((1 << p->n) < N) p->n++;
     if (!build_schedule(N, frozen_mask, L, spc_max, mode, p->sched)) {
         delete p;
@@ -3107,7 +3223,7 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     float best_t = -1.f;
     pscl_launch_cfg cur{};
     // plans already timed: (threads, LDS bytes, workgroups, recompute, fuse)
-    std::vector<std::tuple<int, int, int, int, int>> seen;
+    std::vector<std::tuple<int, int, int, int, int, int>> seen;
     // times one shape (skipped when it builds a plan already timed);
     // remembers the fastest
     auto trial = [&](const pscl_launch_cfg& cfg) {
@@ -3119,8 +3235,8 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
             if (cs != PSCL_E_UNSUPPORTED && cs != PSCL_E_NOMEM) st = cs;
             return;
         }
-        const std::tuple<int, int, int, int, int> key{p->NT, p->lds_bytes, p->grid_max,
-                                                      virtual_depth(p, p->k_glob), p->fuse_k};
+        const std::tuple<int, int, int, int, int, int> key{
+            p->NT, p->lds_bytes, p->grid_max, virtual_depth(p, p->k_glob), p->fuse_k, p->chain};
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
             pscl_plan_destroy(p);
             return;
@@ -3144,7 +3260,7 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
     const int threads[] = {64, 128, 256};
     const int budgets[] = {8192, 10240, 12288, 16384, 20480, 24576, 32768, 49152};
     for (int t : threads)
-        for (int b : budgets) trial(pscl_launch_cfg{t, b, 0, 0, 0});
+        for (int b : budgets) trial(pscl_launch_cfg{t, b, 0, 0, 0, 0});
     // 2. stages recomputed below the root, at the best shape
     const pscl_launch_cfg shape = cur;
     for (int rc = 1; rc <= 3; ++rc) {
@@ -3161,7 +3277,16 @@ pscl_status pscl_autotune(int N, int K, const uint8_t* frozen_mask, uint64_t crc
             trial(c);
         }
     }
-    // 4. residency cap at the best so far (fewer frames per CU)
+    // 4. tree levels per F / G pass
+    {
+        const pscl_launch_cfg lay = cur;
+        for (int u : {1, 2}) {
+            pscl_launch_cfg c = lay;
+            c.unroll = u;
+            trial(c);
+        }
+    }
+    // 5. residency cap at the best so far (fewer frames per CU)
     {
         const pscl_launch_cfg lay = cur;
         for (int cap : {2, 4, 8}) {
@@ -3213,7 +3338,7 @@ pscl_status pscl_autotune_group(const pscl_plan* const* plans, int n_plans, cons
         }
         pscl_group* g = nullptr;
         if (cs == PSCL_OK) {
-            pscl_launch_cfg gc{cfg.threads, 0, 0, 0, 0};
+            pscl_launch_cfg gc{cfg.threads, 0, 0, 0, 0, 0};
             cs = pscl_group_create((const pscl_plan* const*)tp.data(), n_plans, n_jobs, 1, &gc, &g);
         }
         float ms = 0.f;
@@ -3237,7 +3362,7 @@ pscl_status pscl_autotune_group(const pscl_plan* const* plans, int n_plans, cons
         }
     };
     for (int t : {64, 128, 256})
-        for (int b : {8192, 10240, 12288, 16384, 24576, 32768}) trial(pscl_launch_cfg{t, b, 0, 0, 0});
+        for (int b : {8192, 10240, 12288, 16384, 24576, 32768}) trial(pscl_launch_cfg{t, b, 0, 0, 0, 0});
     const pscl_launch_cfg shape = cur;
     for (int rc = 1; rc <= 3; ++rc) {
         pscl_launch_cfg c = shape;
@@ -3249,6 +3374,14 @@ pscl_status pscl_autotune_group(const pscl_plan* const* plans, int n_plans, cons
         for (int fz : {-1, 4, 5}) {
             pscl_launch_cfg c = lay;
             c.fuse_log2 = fz;
+            trial(c);
+        }
+    }
+    {
+        const pscl_launch_cfg lay = cur;
+        for (int u : {1, 2}) {
+            pscl_launch_cfg c = lay;
+            c.unroll = u;
             trial(c);
         }
     }

@@ -157,9 +157,11 @@ def test_launch_cfg_and_autotune_validate_arguments(pk):
         cfg = pk.LaunchCfg(threads, 0, 0)
         assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(cfg),
                                            ctypes.byref(h)) == 1
-    # negative budget; recompute outside 1..3; fused-leaf size outside -1..5
+    # negative budget; recompute outside 1..3; fused-leaf size outside -1..5;
+    # levels per F / G pass outside 1..2
     for bad in (pk.LaunchCfg(64, -1, 0), pk.LaunchCfg(64, 0, 0, 4), pk.LaunchCfg(64, 0, 0, -1),
-                pk.LaunchCfg(64, 0, 0, 0, 6), pk.LaunchCfg(64, 0, 0, 0, -2)):
+                pk.LaunchCfg(64, 0, 0, 0, 6), pk.LaunchCfg(64, 0, 0, 0, -2),
+                pk.LaunchCfg(64, 0, 0, 0, 0, 3), pk.LaunchCfg(64, 0, 0, 0, 0, -1)):
         assert pk.lib.pscl_plan_create_cfg(8, 4, u8, 0, 0, 4, 0, 4, 0, ctypes.byref(bad),
                                            ctypes.byref(h)) == 1
     assert not h.value

@@ -313,6 +313,27 @@ def test_recomputed_stages(dtype, recompute, nk):
         plan.close()
 
 
+# F / G passes of one or two tree levels (unroll 1, 2) in every dtype, at the
+# default LDS budget (chained passes on chip and across the LDS / workspace
+# boundary) and at one small enough that they read and write the workspace
+@pytest.mark.parametrize("dtype", ["f32", "i16", "i8"])
+@pytest.mark.parametrize("unroll", [1, 2])
+@pytest.mark.parametrize("nk", [(1024, 860), (2048, 1723)])
+def test_unrolled_passes(dtype, unroll, nk):
+    import paper_1505_01466_amd as pk
+
+    N, K = nk
+    code, b = batch(N, K, 32, synth.CRC32_POLY, 4.0, 96, 3.5, (63, N, unroll), dtype)
+    ref = oracle_decode(code, 32, b.llr, dtype)
+    for budget in (0, 8192):
+        plan = pk.Plan(N, K, code.frozen, code.poly, 32, 32, dtype, unroll=unroll,
+                       lds_budget=budget)
+        _say(f"({N},{K}) L=32 {dtype} unroll={unroll} budget={budget}: {plan.info()}")
+        g = gpu_decode(code, 32, b.llr, dtype, plan=plan)
+        compare(g, ref, dtype, f"unroll={unroll} budget={budget}")
+        plan.close()
+
+
 @pytest.mark.parametrize("fuse", [-1, 1, 3, 4, 5])
 @pytest.mark.parametrize("L", [2, 8, 32])
 def test_fused_fork_sizes(fuse, L):
