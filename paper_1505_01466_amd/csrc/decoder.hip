@@ -750,6 +750,56 @@ DEV void pp_fg_chain(const Ctx<T>& c, const OpRec& op, int y2, int k, const Grp&
     }
 }
 
+// The F / G below the root reading the recomputed stage (as pp_fg_virtual)
+// chained with its left child's F: for each output chunk e of the child's F,
+// the node's output chunks e and H + e (four channel chunks each), both
+// stored, and their F.
+template <typename T, bool IS_G, int OSP1, int OSP2>
+DEV void pp_fg_virtual_chain(const Ctx<T>& c, const OpRec& op, int y2, int k, const Grp& q) {
+    using CF = ChunkFG<T>;
+    constexpr int LOGV = VecIO<T>::LOGV;
+    if (!q.valid) return;
+    const int M = 1 << (k - 1);  // the node's outputs; the channel has 4M values
+    const int H = M >> 1;
+    const bool right = op_side(op) != 0;
+    const T* ch = c.chan;
+    T* mid = c.template stage<OSP1>(op.y, k - 1, q.p);
+    T* out = c.template stage<OSP2>(y2, k - 2, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.template bw<OSP1>(op.z, k - 1, c.srcB(k - 1, q.p));
+    const uint32_t* br = right ? c.template bw<SP_WS>(op.x, k, c.srcB(k, q.p)) : nullptr;
+    auto bits = [&](const uint32_t* w, int e) { return w[e >> 5] >> (e & 31); };
+    auto node_out = [&](int e) {
+        const uint4 c0 = CF::clamp(*(const uint4*)(ch + e));
+        const uint4 c2 = CF::clamp(*(const uint4*)(ch + 2 * M + e));
+        const uint4 c1 = CF::clamp(*(const uint4*)(ch + M + e));
+        const uint4 c3 = CF::clamp(*(const uint4*)(ch + 3 * M + e));
+        uint4 x, y;
+        if (right) {
+            x = CF::g(c0, c2, bits(br, e));
+            y = CF::g(c1, c3, bits(br, M + e));
+        } else {
+            x = CF::f(c0, c2);
+            y = CF::f(c1, c3);
+        }
+        if constexpr (IS_G) return CF::g(x, y, bits(bl, e));
+        else return CF::f(x, y);
+    };
+    const int nch = H >> LOGV;
+    for (int ch0 = q.g; ch0 < nch; ch0 += q.G) {
+        const int e = ch0 << LOGV;
+        const uint4 a = node_out(e);
+        const uint4 b = node_out(H + e);
+        *(uint4*)(mid + e) = a;
+        *(uint4*)(mid + H + e) = b;
+        *(uint4*)(out + e) = CF::f(a, b);
+    }
+    if (q.g == 0) {
+        c.setA(k - 1, q.p);
+        c.setA(k - 2, q.p);
+    }
+}
+
 // The chained form's spaces: input, node output and child output, each in
 // LDS or the workspace, a level in LDS only if every level below it is.
 template <typename T, bool IS_G>
@@ -758,6 +808,15 @@ DEV void pp_fg_chain_any(const Ctx<T>& c, const OpRec& op, uint64_t next, int k,
     const int osp = op_osp(op);
     const int y2 = (int)(uint16_t)(next >> 32);
     const int osp2 = ((int)(uint16_t)next >> 14) & 3;
+    if constexpr (std::is_same<T, float>::value) {
+        // the recomputed stage below the root (chained for float32 only)
+        if (isp == SP_VT) {
+            if (osp == SP_LDS) pp_fg_virtual_chain<T, IS_G, SP_LDS, SP_LDS>(c, op, y2, k, q);
+            else if (osp2 == SP_LDS) pp_fg_virtual_chain<T, IS_G, SP_WS, SP_LDS>(c, op, y2, k, q);
+            else pp_fg_virtual_chain<T, IS_G, SP_WS, SP_WS>(c, op, y2, k, q);
+            return;
+        }
+    }
     if (isp == SP_LDS) pp_fg_chain<T, IS_G, SP_LDS, SP_LDS, SP_LDS>(c, op, y2, k, q);
     else if (osp == SP_LDS) pp_fg_chain<T, IS_G, SP_WS, SP_LDS, SP_LDS>(c, op, y2, k, q);
     else if (osp2 == SP_LDS) pp_fg_chain<T, IS_G, SP_WS, SP_WS, SP_LDS>(c, op, y2, k, q);
@@ -2733,7 +2792,11 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
             OpRec& b = out[i + 1];
             const int ta = f_type(a), ka = f_k(a), ia = f_isp(a);
             if (ta != OP_F && ta != OP_G) continue;
-            if (ia != SP_LDS && ia != SP_WS) continue;
+            // the recomputed stage below the root chains too for float32
+            // (the level n - 2 stage is then never re-read by its F; time
+            // unchanged); int16 lost 2.4 % to the registers of its eight
+            // channel chunks per output chunk
+            if (ia != SP_LDS && ia != SP_WS && !(ia == SP_VT && p->dtype == PSCL_F32)) continue;
             if (((a.meta >> 8) & 15) != 0) continue;
             if (f_type(b) != OP_F || f_k(b) != ka - 1 || f_isp(b) != f_osp(a) || b.x != a.y)
                 continue;
