@@ -1535,7 +1535,8 @@ DEV void pp_emit_pending(Ctx<T>& c, const OpRec& op, bool prune, const Grp& q) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc, int P) {
+DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc, int P,
+                   uint64_t praw) {
     using D = Dom<T>;
     using A = typename D::A;
     using S = typename D::S;
@@ -1559,6 +1560,24 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
                       : isp == SP_LDS ? (const T*)c.template stage<SP_LDS>(op.x, k, c.srcA(k, s))
                                       : (const T*)c.template stage<SP_WS>(op.x, k, c.srcA(k, s));
         const bool clamp = isp == SP_CH;
+        // op.z = 1 / 2: the previous record, the F / G forming this leaf's
+        // input, did nothing, and the leaf's values are formed here from
+        // that record's input stage (and, for a G, the left partial sums)
+        // with the same arithmetic, never stored
+        const int fz = op.z;
+        const T* pin = nullptr;
+        uint32_t pbits = 0;
+        if (fz) {
+            const int pisp = ((int)(uint16_t)praw >> 12) & 3;
+            const int posp = ((int)(uint16_t)praw >> 14) & 3;
+            const int px = (int)(uint16_t)(praw >> 16), pz = (int)(uint16_t)(praw >> 48);
+            pin = pisp == SP_LDS
+                      ? (const T*)c.template stage<SP_LDS>(px, k + 1, c.srcA(k + 1, s))
+                      : (const T*)c.template stage<SP_WS>(px, k + 1, c.srcA(k + 1, s));
+            if (fz == 2)
+                pbits = posp == SP_LDS ? *c.template bw<SP_LDS>(pz, k, c.srcB(k, s))
+                                       : *c.template bw<SP_WS>(pz, k, c.srcB(k, s));
+        }
         const M pms = c.pm()[s];
         uint64_t key[8];
         auto put = [&](int r, M v) {
@@ -1571,7 +1590,19 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
         // the node's values, one at a time (at most 32)
         auto scan = [&](auto fn) {
             using IO = VecIO<T>;
-            if (nv >= IO::V) {
+            if (fz) {
+                // at least one chunk, at most 32 values (one partial-sum word)
+                for (int ch = 0; ch < (nv >> IO::LOGV); ++ch) {
+                    const int e = ch << IO::LOGV;
+                    const uint4 x = *(const uint4*)(pin + e);
+                    const uint4 y = *(const uint4*)(pin + nv + e);
+                    const uint4 q0 = fz == 2 ? ChunkFG<T>::g(x, y, pbits >> e) : ChunkFG<T>::f(x, y);
+                    A v[IO::V];
+                    IO::unpack(q0, v);
+#pragma unroll
+                    for (int j = 0; j < IO::V; ++j) fn(e + j, v[j]);
+                }
+            } else if (nv >= IO::V) {
                 for (int ch = 0; ch < (nv >> IO::LOGV); ++ch) {
                     const uint4 q0 = *(const uint4*)(in + (ch << IO::LOGV));
                     A v[IO::V];
@@ -1998,6 +2029,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
     OpRec pop{};
     int pprune = 0;
     uint64_t nraw = sched[0];
+    uint64_t praw = 0;  // the previous record
     for (int oi = 0; oi < a.n_ops; ++oi) {
         const uint64_t raw = nraw;
         nraw = sched[oi + 1 < a.n_ops ? oi + 1 : oi];
@@ -2040,7 +2072,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                     // faster for float32 only, whose workgroups span two
                     // wavefronts; its networks hold at most 32 paths)
                     if (k <= a.fuse_k) {
-                        P = fork_small<T>(c, op, type, k, side, cc, P);
+                        P = fork_small<T>(c, op, type, k, side, cc, P, praw);
                         q = make_grp(c.tid, c.NT, P);
                         __syncthreads();
                         break;
@@ -2065,6 +2097,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                 break;
             }
         }
+        praw = raw;
         wave_sync();
     }
     if (pend) pp_emit_pending<T>(c, pop, pprune, q);
@@ -2456,6 +2489,7 @@ struct pscl_plan {
     int recompute = 0;  // stages below the root recomputed at most (0..2)
     int fuse_k = -1;    // float32 fused forks up to 2^fuse_k values (-1: none)
     int chain = 0;      // F / G chained with the left child's F when it follows (0 / 1)
+    std::vector<OpRec> recs;  // the operation records (a host copy of d_ops)
     const void* kernel = nullptr;
     std::vector<uint8_t> frozen;
 };
@@ -2659,9 +2693,28 @@ int layout(const pscl_plan* p, int k_glob, Layout& lay, KArgs& a) {
         return v;
     };
     for (int k = 0; k < MAXLVL; ++k) lay.a_off[k] = lay.bl_off[k] = lay.br_off[k] = 0;
+    // the levels the schedule touches: the LLR stage of level k is read or
+    // written by an F / G at level k or k + 1 or a leaf at level k, the
+    // partial sums of level k by a leaf or Combine at level k or a Combine
+    // or G at level k + 1 (a code whose leaves all sit above level 0 has no
+    // level-0 buffers)
+    bool st_need[MAXLVL + 1] = {}, ps_need[MAXLVL + 1] = {};
+    for (const SchedOp& s : p->sched) {
+        const bool fg = s.type == OP_F || s.type == OP_G;
+        if (fg) {
+            st_need[s.k] = true;
+            if (s.k >= 1) st_need[s.k - 1] = true;
+        } else if (s.type != OP_COMB) {
+            st_need[s.k] = true;
+        }
+        if (!fg) ps_need[s.k] = true;
+        if ((s.type == OP_COMB || s.type == OP_G) && s.k >= 1) ps_need[s.k - 1] = true;
+    }
+    ps_need[n] = true;
     for (int k = 0; k < n; ++k)  // the stages below the root are not stored when recomputed
-        lay.a_off[k] = (k >= n - vd) ? 0 : place(L * (1 << k) * es, k < k_glob);
+        lay.a_off[k] = (k >= n - vd || !st_need[k]) ? 0 : place(L * (1 << k) * es, k < k_glob);
     for (int k = 0; k <= n; ++k) {
+        if (!ps_need[k]) continue;
         const int bytes = L * words_host(k) * 4;
         if (k < n) lay.bl_off[k] = place(bytes, k < k_glob);  // the root is never a left child
         lay.br_off[k] = place(bytes, k < k_glob);
@@ -2804,6 +2857,26 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
             a.meta = (uint16_t)(a.meta | (4u << 8));
             b.meta = (uint16_t)(OP_NOP | ((uint32_t)f_osp(b) << 14));
             ++i;
+        }
+        if (p->dtype == PSCL_F32 && p->fuse_k >= 2) {
+            // a forking leaf run fused in one wavefront (float32, 4 to
+            // 2^fuse_k values) right after the F / G forming its input: the
+            // leaf forms its values from that F / G's input stage (z = 1
+            // after an F, 2 after a G) and the F / G record becomes a no-op
+            // keeping everything but its type (after the chains: F / G
+            // records they hold are not taken; measured slightly faster
+            // than the other order)
+            for (size_t i = 1; i < out.size(); ++i) {
+                OpRec& a = out[i - 1];
+                OpRec& b = out[i];
+                const int tb = f_type(b), kb = f_k(b), ta = f_type(a), ia = f_isp(a);
+                if (tb != OP_REP && tb != OP_R1 && tb != OP_SPC) continue;
+                if (kb < 2 || kb > p->fuse_k || (ta != OP_F && ta != OP_G)) continue;
+                if (f_k(a) != kb + 1 || (ia != SP_LDS && ia != SP_WS)) continue;
+                if (((a.meta >> 8) & 15) != 0 || a.y != b.x || f_osp(a) != f_isp(b)) continue;
+                b.z = (uint16_t)(ta == OP_F ? 1 : 2);
+                a.meta = (uint16_t)((a.meta & ~7u) | OP_NOP);
+            }
         }
     }
     return out;
@@ -3093,6 +3166,7 @@ pscl_status pscl_plan_create_cfg(int N, int K, const uint8_t* frozen_mask, uint6
     p->grid_max = occ * prop.multiProcessorCount;
 
     std::vector<OpRec> ops = make_records(p, lay, k_glob);
+    p->recs = ops;
     std::vector<uint64_t> syn(N, 0);
     if (crc_len > 0) syn = crc_codeword_table(N, frozen_mask, crc_poly, crc_len);
     std::vector<uint16_t> info;
@@ -3536,8 +3610,24 @@ pscl_status pscl_group_create(const pscl_plan* const* plans, int n_plans, int ma
     int64_t base = 0;
     for (int i = 0; i < n_plans && st == PSCL_OK; ++i) {
         const pscl_plan* p = plans[i];
-        st = hip_status(hipMemcpy(g->d_sched + base, p->d_ops, (size_t)p->args.n_ops * 8,
-                                  hipMemcpyDeviceToDevice));
+        if (g->wide && p->fuse_k >= 0) {
+            // the kernels for lists above 32 paths run no fused forks: a
+            // leaf that forms its values from its parent's stage gets its
+            // F / G record back
+            std::vector<OpRec> r = p->recs;
+            for (size_t j = 1; j < r.size(); ++j) {
+                const int t = r[j].meta & 7;
+                if (r[j].z && (t == OP_REP || t == OP_R1 || t == OP_SPC)) {
+                    r[j - 1].meta = (uint16_t)((r[j - 1].meta & ~7u) | (r[j].z == 1 ? OP_F : OP_G));
+                    r[j].z = 0;
+                }
+            }
+            st = hip_status(hipMemcpy(g->d_sched + base, r.data(), (size_t)p->args.n_ops * 8,
+                                      hipMemcpyHostToDevice));
+        } else {
+            st = hip_status(hipMemcpy(g->d_sched + base, p->d_ops, (size_t)p->args.n_ops * 8,
+                                      hipMemcpyDeviceToDevice));
+        }
         dp[i].a = p->args;
         dp[i].a.ws = nullptr;
         dp[i].op_base = base;

@@ -78,6 +78,37 @@ def test_group_equals_single_plan_decodes(env, dtype):
     g.close()
 
 
+def test_wide_group_with_short_lists(env):
+    """A group holding a list above 32 paths runs the wide kernels, which
+    have no fused forks: float32 plans of shorter lists (whose records let
+    fused forks form their leaf values from the parent's stage) must give
+    the same frames there as alone, and match the oracle."""
+    pk, torch = env
+    specs = [(1024, 860, 32, synth.CRC32_POLY, 4.0, 32, 3.5),
+             (512, 256, 8, synth.CRC8_POLY, 2.5, 8, 2.0),
+             (1024, 860, 32, synth.CRC32_POLY, 4.0, 64, 3.5)]
+    plans, work, host, codes = [], [], [], []
+    for i, (N, K, r, poly, d, L, e) in enumerate(specs):
+        code = synth.make_code(N, K, r, poly, d)
+        codes.append((code, L))
+        plans.append(pk.Plan(N, K, code.frozen, code.poly, r, L, "f32"))
+        b = synth.make_batch(code, 48, e, (71, i), "f32")
+        host.append(b.llr)
+        work.append((i, torch.from_numpy(b.llr).cuda()))
+    g = pk.Group(plans, max_jobs=8)
+    outs = g.decode(work)
+    torch.cuda.synchronize()
+    for j, ((pi, llr), out) in enumerate(zip(work, outs)):
+        _say(f"wide group job {j}: L={codes[pi][1]}")
+        alone = plans[pi].decode(llr)
+        torch.cuda.synchronize()
+        assert _same([o.cpu().numpy() for o in out], [a.cpu().numpy() for a in alone]), j
+        code, L = codes[pi]
+        compare(tuple(o.cpu().numpy() for o in out), oracle_decode(code, L, host[j], "f32"),
+                "f32", f"wide group job {j}")
+    g.close()
+
+
 @pytest.mark.parametrize("dtype", ["i8", "f32"])
 def test_autotuned_group_against_oracle(env, dtype):
     """pscl_autotune_group on a mixed batch, plans rebuilt with the tuned
