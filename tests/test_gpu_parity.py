@@ -272,6 +272,41 @@ def test_oneshot_entry_point():
     assert (u.cpu().numpy() == o[0]).all() and (ok.cpu().numpy() == o[1]).all()
 
 
+def test_oneshot_calls_overlapping_on_streams():
+    """The one-call entry point caches one group per code; calls for the same
+    code issued on several streams without synchronising in between each get
+    their own workspace and counter, so each equals its own solo decode."""
+    import torch
+
+    import paper_1505_01466_amd as pk
+
+    code, _ = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 4, 2.5, 81, "i8")
+    inputs = []
+    for i in range(4):
+        _, b = batch(1024, 512, 8, synth.CRC8_POLY, 2.5, 300 + 37 * i, 2.5, (82, i), "i8")
+        inputs.append((b.llr, torch.from_numpy(b.llr).cuda()))
+    solo = []
+    for _, llr in inputs:
+        solo.append(pk.decode(code.N, code.K, code.frozen, code.poly, code.r, 8, llr, "i8"))
+        torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for st, (_, llr) in zip(streams, inputs):
+        with torch.cuda.stream(st):
+            outs.append(pk.decode(code.N, code.K, code.frozen, code.poly, code.r, 8, llr, "i8"))
+    for st in streams:
+        torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    for i, (out, ref) in enumerate(zip(outs, solo)):
+        _say(f"overlapping one-call decode {i}: {inputs[i][0].shape[0]} frames")
+        for x, y in zip(out, ref):
+            assert x.cpu().numpy().tobytes() == y.cpu().numpy().tobytes(), i
+    o = oracle_decode(code, 8, inputs[0][0], "i8")
+    assert (outs[0][0].cpu().numpy() == o[0]).all() and (outs[0][1].cpu().numpy() == o[1]).all()
+
+
 def test_autotuned_launch_shape():
     import paper_1505_01466_amd as pk
     import torch
