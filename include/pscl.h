@@ -161,7 +161,8 @@ typedef struct {
     /* Tree levels one F / G pass descends (the unrolling of Sec. II-D at
      * the granularity of node operations): 1 = each F and G its own pass;
      * 2 = an F or G immediately followed by the F of its left child runs as
-     * one pass that stores both outputs without re-reading the first, and
+     * one pass that stores both outputs without re-reading the first
+     * (float32: three levels when the grandchild's F follows as well), and
      * (float32, forking leaves run in one wavefront) a leaf right after the
      * F or G forming its input forms its values from that operation's input
      * instead of their being stored and read back (0 = default 2). */

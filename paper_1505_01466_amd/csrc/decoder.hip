@@ -750,6 +750,58 @@ DEV void pp_fg_chain(const Ctx<T>& c, const OpRec& op, int y2, int k, const Grp&
     }
 }
 
+// Three tree levels in one pass (float32): an F or G at a level-k node, the
+// F of its left child and the F of that child's left child, the two F
+// records then doing nothing.  For each output chunk e of the last F
+// (Q = 2^(k-3) outputs), a lane loads the eight input chunks e + jQ, forms
+// the node's four output chunks e + jQ (j < 4), the child's two (e, Q + e)
+// and the grandchild's one, and stores all seven; no stage is re-read.
+template <typename T, bool IS_G, int ISP, int OSP1, int OSP2, int OSP3>
+DEV void pp_fg_chain3(const Ctx<T>& c, const OpRec& op, int y2, int y3, int k, const Grp& q) {
+    using CF = ChunkFG<T>;
+    constexpr int LOGV = VecIO<T>::LOGV;
+    if (!q.valid) return;
+    const int M = 1 << (k - 1);  // the node's outputs
+    const int Q = M >> 2;        // the grandchild's F outputs
+    const T* in = c.template stage<ISP>(op.x, k, c.srcA(k, q.p));
+    T* m1 = c.template stage<OSP1>(op.y, k - 1, q.p);
+    T* m2 = c.template stage<OSP2>(y2, k - 2, q.p);
+    T* m3 = c.template stage<OSP3>(y3, k - 3, q.p);
+    const uint32_t* bl = nullptr;
+    if constexpr (IS_G) bl = c.template bw<OSP1>(op.z, k - 1, c.srcB(k - 1, q.p));
+    const int nch = Q >> LOGV;
+    for (int ch = q.g; ch < nch; ch += q.G) {
+        const int e = ch << LOGV;
+        uint4 a[4], b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[j] = *(const uint4*)(in + e + j * Q);
+            b[j] = *(const uint4*)(in + M + e + j * Q);
+        }
+        uint4 x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (IS_G) {
+                const int i = e + j * Q;
+                x[j] = CF::g(a[j], b[j], bl[i >> 5] >> (i & 31));
+            } else {
+                x[j] = CF::f(a[j], b[j]);
+            }
+            *(uint4*)(m1 + e + j * Q) = x[j];
+        }
+        const uint4 y0 = CF::f(x[0], x[2]);
+        const uint4 y1 = CF::f(x[1], x[3]);
+        *(uint4*)(m2 + e) = y0;
+        *(uint4*)(m2 + Q + e) = y1;
+        *(uint4*)(m3 + e) = CF::f(y0, y1);
+    }
+    if (q.g == 0) {
+        c.setA(k - 1, q.p);
+        c.setA(k - 2, q.p);
+        c.setA(k - 3, q.p);
+    }
+}
+
 // The F / G below the root reading the recomputed stage (as pp_fg_virtual)
 // chained with its left child's F: for each output chunk e of the child's F,
 // the node's output chunks e and H + e (four channel chunks each), both
@@ -803,11 +855,31 @@ DEV void pp_fg_virtual_chain(const Ctx<T>& c, const OpRec& op, int y2, int k, co
 // The chained form's spaces: input, node output and child output, each in
 // LDS or the workspace, a level in LDS only if every level below it is.
 template <typename T, bool IS_G>
-DEV void pp_fg_chain_any(const Ctx<T>& c, const OpRec& op, uint64_t next, int k, const Grp& q) {
+DEV void pp_fg_chain_any(const Ctx<T>& c, const OpRec& op, uint64_t next, uint64_t next2, int k,
+                         const Grp& q) {
     const int isp = op_isp(op);
     const int osp = op_osp(op);
     const int y2 = (int)(uint16_t)(next >> 32);
     const int osp2 = ((int)(uint16_t)next >> 14) & 3;
+    if constexpr (std::is_same<T, float>::value) {
+        if (op_cand(op) & 2) {
+            // three levels (candidate bit 1): the record after next holds the
+            // grandchild's F output
+            const int y3 = (int)(uint16_t)(next2 >> 32);
+            const int osp3 = ((int)(uint16_t)next2 >> 14) & 3;
+            if (isp == SP_LDS)
+                pp_fg_chain3<T, IS_G, SP_LDS, SP_LDS, SP_LDS, SP_LDS>(c, op, y2, y3, k, q);
+            else if (osp == SP_LDS)
+                pp_fg_chain3<T, IS_G, SP_WS, SP_LDS, SP_LDS, SP_LDS>(c, op, y2, y3, k, q);
+            else if (osp2 == SP_LDS)
+                pp_fg_chain3<T, IS_G, SP_WS, SP_WS, SP_LDS, SP_LDS>(c, op, y2, y3, k, q);
+            else if (osp3 == SP_LDS)
+                pp_fg_chain3<T, IS_G, SP_WS, SP_WS, SP_WS, SP_LDS>(c, op, y2, y3, k, q);
+            else
+                pp_fg_chain3<T, IS_G, SP_WS, SP_WS, SP_WS, SP_WS>(c, op, y2, y3, k, q);
+            return;
+        }
+    }
     if constexpr (std::is_same<T, float>::value) {
         // the recomputed stage below the root (chained for float32 only)
         if (isp == SP_VT) {
@@ -2012,6 +2084,14 @@ DEV void bind_plan(Ctx<T>& c, const KArgs& a, uint8_t* wsb) {
     c.vt2_off = a.vt2_off;
 }
 
+// The record after next for a three-level pass (float32 only).
+template <typename T>
+DEV uint64_t chain3_next(const uint64_t* __restrict__ sched, int oi, int cc) {
+    if constexpr (std::is_same<T, float>::value)
+        if (cc & 2) return sched[oi + 2];
+    return 0;
+}
+
 // Schedule records are read with scalar loads (sched points into a
 // read-only kernel argument), the next one while the current operation
 // runs.  Outputs go to entry f of u_hat / crc_ok / pm_out.
@@ -2051,11 +2131,11 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
         }
         switch (type) {
             case OP_F:
-                if (cc & 4) pp_fg_chain_any<T, false>(c, op, nraw, k, q);
+                if (cc & 4) pp_fg_chain_any<T, false>(c, op, nraw, chain3_next<T>(sched, oi, cc), k, q);
                 else pp_fg_any<T, false>(c, op, k, q);
                 break;
             case OP_G:
-                if (cc & 4) pp_fg_chain_any<T, true>(c, op, nraw, k, q);
+                if (cc & 4) pp_fg_chain_any<T, true>(c, op, nraw, chain3_next<T>(sched, oi, cc), k, q);
                 else pp_fg_any<T, true>(c, op, k, q);
                 break;
             case OP_COMB:
@@ -2854,6 +2934,21 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
             if (f_type(b) != OP_F || f_k(b) != ka - 1 || f_isp(b) != f_osp(a) || b.x != a.y)
                 continue;
             if (ka < 2 || (1 << (ka - 2)) < V) continue;
+            // float32: a third level when the grandchild's F follows too
+            // (+1 %; the integer kernels stay at two, their registers being
+            // at the limit of their residency)
+            if (p->dtype == PSCL_F32 && ia != SP_VT && i + 2 < out.size() && ka >= 3 &&
+                (1 << (ka - 3)) >= V) {
+                OpRec& c3 = out[i + 2];
+                if (f_type(c3) == OP_F && f_k(c3) == ka - 2 && f_isp(c3) == f_osp(b) &&
+                    c3.x == b.y) {
+                    a.meta = (uint16_t)(a.meta | (6u << 8));
+                    b.meta = (uint16_t)(OP_NOP | ((uint32_t)f_osp(b) << 14));
+                    c3.meta = (uint16_t)(OP_NOP | ((uint32_t)f_osp(c3) << 14));
+                    i += 2;
+                    continue;
+                }
+            }
             a.meta = (uint16_t)(a.meta | (4u << 8));
             b.meta = (uint16_t)(OP_NOP | ((uint32_t)f_osp(b) << 14));
             ++i;
