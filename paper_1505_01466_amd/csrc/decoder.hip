@@ -387,6 +387,12 @@ struct ChunkFG<int8_t> {
 //   leaves:   x = LLR stage k (in_space), y = output partial sums of level k
 //             (out_space).
 // Offsets are in 16-byte units in LDS and 256-byte units in the workspace.
+// Fused records: an F / G with candidate bit 2 also runs the next record's
+// F (bit 1: and the F after it, float32), those records becoming no-ops
+// that keep their output offset and space; the stage below the root uses
+// candidate bits 3 (two recomputed levels) and 0 (under a right child).  A
+// float32 forking leaf with z = 1 / 2 forms its values from the previous
+// record, an F / G turned no-op with its other fields kept.
 struct OpRec {
     uint16_t meta, x, y, z;
 };
