@@ -852,7 +852,7 @@ def main():
     out = {
         "metric": "info Gbps @ (2048,1723) CRC32 L=32",
         "p99_latency_us": None if serving is None else next(
-            (serving["100000"][m]["p99_us"] for m in ("server", "persistent", "per_request")
+            (serving["100000"][m]["p99_us"] for m in ("persistent", "server", "per_request")
              if m in serving["100000"]), None),
         "fer_vs_oracle": None if cpu is None else cpu["fer_vs_oracle"],
         "value": round(value, 4),

@@ -363,10 +363,12 @@ pscl_status pscl_decode_mixed(const pscl_plan* const* plans, int n_plans, const 
  * claims published frames one at a time and decodes them, so a request
  * starts as soon as any workgroup is free (continuous batching at frame
  * granularity); the last frame of a request writes its ticket to the
- * request's completion word.  Only the first active_per_cu resident
- * workgroups of each CU take frames: by default at least four and more as
- * frames queue up, so that at low load few frames share a CU (lower
- * latency) and under load every resident workgroup works.  The kernel ends after idle_us microseconds
+ * request's completion word.  Workgroups are ranked by start order on
+ * their CU: the first active_per_cu of each CU take frames, or by default
+ * the one of rank r while more than r x (CU count) frames are outstanding
+ * (published, not yet finished), so that at low load few frames share a
+ * CU (lower latency) and under load every resident workgroup works.  The
+ * kernel ends after idle_us microseconds
  * without work (so it never outlives the server) and is relaunched when
  * requests are held.  `streams`, max_batch_frames and max_batch_requests
  * do not apply; at most 2^18 frames are published and unfinished at once
@@ -395,7 +397,7 @@ typedef struct {
     int wg_per_cu;  /* persistent mode: resident workgroups per CU at most (0 = as
                        many as fit) */
     int active_per_cu; /* persistent mode: resident workgroups per CU that take
-                          frames (0 = adaptive: max(4, frames outstanding per CU)) */
+                          frames (0 = by the frames outstanding, as above) */
 } pscl_server_cfg;
 
 /* Create a server on the current device (allocates one group, stream and

@@ -2345,16 +2345,28 @@ DEV unsigned long long ring_refresh(const pscl_ring::Args& r, unsigned long long
 DEV int ring_admit(const pscl_ring::Args& r, uint32_t rank) {
     constexpr int AG = __HIP_MEMORY_SCOPE_AGENT;
     pscl_ring::Dev* dv = r.dev;
+    // the workgroup of rank r on its CU takes frames while r is below the
+    // host's fixed count `active`, or, with none set, while more than
+    // r x CUs frames are outstanding (published, not yet finished): one or
+    // two frames per CU at low load, every resident workgroup under load,
+    // following the load as it is on the device
+    auto wanted = [&]() {
+        const uint32_t act = __hip_atomic_load(&dv->active, __ATOMIC_RELAXED, AG);
+        if (act) return rank < act;
+        const unsigned long long pub = __hip_atomic_load(&dv->published, __ATOMIC_RELAXED, AG);
+        const unsigned long long dn = __hip_atomic_load(&dv->done, __ATOMIC_RELAXED, AG);
+        return pub > dn && pub - dn > (unsigned long long)rank * r.cus;
+    };
     // the first workgroup of every CU always takes frames (and, waiting for
     // tickets, refreshes the device copies, `active` among them)
-    if (rank == 0 || rank < __hip_atomic_load(&dv->active, __ATOMIC_RELAXED, AG)) return 1;
+    if (rank == 0 || wanted()) return 1;
     uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     const uint64_t idle = (uint64_t)r.idle_us * 100u;
     const uint32_t max_polls = r.idle_us / 16u + 64u;
     unsigned long long last = __hip_atomic_load(&dv->published, __ATOMIC_RELAXED, AG);
     for (uint32_t poll = 0;; ++poll) {
         for (int i = 0; i < 16; ++i) __builtin_amdgcn_s_sleep(127);
-        if (rank < __hip_atomic_load(&dv->active, __ATOMIC_RELAXED, AG)) return 1;
+        if (wanted()) return 1;
         if (__hip_atomic_load(&dv->stop, __ATOMIC_RELAXED, AG)) return 0;
         const unsigned long long now = __hip_atomic_load(&dv->published, __ATOMIC_RELAXED, AG);
         if (now != last) {  // progress: the idle clock restarts
@@ -2477,6 +2489,7 @@ __global__ void PSCL_KERNEL_BOUNDS(T)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (c.tid == 0) {
+            __hip_atomic_fetch_add(&r.dev->done, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t s = d.slot;
             const uint32_t prev =
                 __hip_atomic_fetch_add(r.count + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

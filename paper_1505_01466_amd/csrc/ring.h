@@ -5,10 +5,10 @@
 // The host publishes requests into memory both sides see coherently
 // (pinned, coherent host memory): a record per published frame (its rows,
 // its request's slot, ticket, plan and frame count; frames are numbered
-// globally in publication order) and the count of published frames.  A persistent kernel's
-// workgroups claim published frames one at a time (a compare-and-swap on a
-// device counter, so only published frames are ever claimed), decode them
-// with their request's plan, and count them per slot; the last frame of a
+// globally in publication order) and the count of published frames.  A
+// persistent kernel's workgroups take frames one at a time by ticket (see
+// Dev), decode them with their request's plan, and count them per slot (and
+// all of them in Dev::done); the last frame of a
 // request writes the request's ticket to its completion word.  A workgroup
 // leaves when the host raises `stop` or after `idle_us` microseconds without
 // a frame to claim, so every launch ends on its own; the host relaunches
@@ -40,7 +40,8 @@ static_assert(sizeof(Rec) == 64, "a frame record is eight 8-byte words");
 struct Ctl {
     uint64_t published;  // frames published so far
     uint32_t stop;       // 1: every workgroup leaves at its next claim
-    uint32_t active;     // workgroups per CU that take frames (by launch rank)
+    uint32_t active;     // workgroups per CU that take frames (by launch rank;
+                         // 0: as many as the frames outstanding call for)
 };
 
 // Device-side state.  A free workgroup takes a ticket, the number of the
@@ -61,6 +62,7 @@ struct Dev {
     alignas(128) uint32_t lease;           // 1 while a workgroup reads host memory
     alignas(128) uint32_t stop;
     uint32_t active;                       // latest `active` seen
+    alignas(128) unsigned long long done;  // frames finished so far (every launch)
     alignas(128) uint32_t orphan_n[2];     // tickets left by the launch of each parity
     uint32_t orphan_take[2];               // of those, taken by the next launch
 };

@@ -275,12 +275,10 @@ void pscl_server::run_ring() {
                 progress = true;
             }
         }
-        // workgroups per CU taking frames: at least four, and as many as the
-        // frames outstanding per CU (all, under load)
+        // workgroups per CU taking frames: a fixed count, or 0 (the kernel
+        // admits workgroups by the frames outstanding on the device)
         {
-            const int64_t per_cu = (ring_frames + cus - 1) / cus;
-            const uint32_t want = active_cfg > 0 ? (uint32_t)active_cfg
-                                                 : (uint32_t)std::min<int64_t>(1024, std::max<int64_t>(4, per_cu));
+            const uint32_t want = active_cfg > 0 ? (uint32_t)active_cfg : 0u;
             if (want != active_set) {
                 __atomic_store_n(&ctl->active, want, __ATOMIC_RELEASE);
                 active_set = want;
