@@ -330,6 +330,26 @@ def test_persistent_server_replay_and_producer_order(env):
     gen.close()
 
 
+@pytest.mark.parametrize("active", [1, 3])
+def test_persistent_server_fixed_active_per_cu(env, active):
+    """A fixed count of workgroups per CU taking frames (by default they are
+    admitted by the frames outstanding on the device): every request equals
+    decoding it alone."""
+    pk, torch, codes, plans = env
+    n = 120
+    work = _requests(torch, codes, n, 13 + active)
+    ref = _alone(torch, plans, work)
+    rng = np.random.default_rng(5 + active)
+    arrivals = np.cumsum(rng.exponential(1e6 / 50000.0, n))
+    sv = pk.Server(plans, persistent=True, active_per_cu=active)
+    outs, lat, elapsed = pk.replay(plans, work, arrivals, server=sv)
+    torch.cuda.synchronize()
+    _check(outs, ref)
+    _say(f"persistent replay, {active} per CU: p50 {np.percentile(lat, 50):.0f} us, "
+         f"p99 {np.percentile(lat, 99):.0f} us")
+    sv.close()
+
+
 def test_persistent_server_wraps_the_frame_records(env):
     """More frames through one persistent-mode server than its ring holds
     frame records (2^18), so every record position is reused, including
