@@ -1623,7 +1623,6 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
     const int C = P * cc;
     const int lc = ilog2u(cc);
     const bool prune = C > L;
-    const int isp = op_isp(op), osp = op_osp(op);
     // wavefront 0 reads every path's input, which other wavefronts may have
     // just written
     if (c.NT > 64) __syncthreads();
@@ -1632,12 +1631,10 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
         const bool act = lane < P;
         const int s = act ? lane : 0;  // idle lanes score path 0 and are ignored
         const int nv = 1 << k;
-        // the input and output spaces vary by level; generic pointers keep
-        // one copy of this code
-        const T* in = isp == SP_CH    ? c.chan
-                      : isp == SP_LDS ? (const T*)c.template stage<SP_LDS>(op.x, k, c.srcA(k, s))
-                                      : (const T*)c.template stage<SP_WS>(op.x, k, c.srcA(k, s));
-        const bool clamp = isp == SP_CH;
+        // leaves run here only with their input and output in LDS (the
+        // others take the three-pass form), so every access is an LDS one
+        const T* in = c.template stage<SP_LDS>(op.x, k, c.srcA(k, s));
+        const bool clamp = false;
         // op.z = 1 / 2: the previous record, the F / G forming this leaf's
         // input, did nothing, and the leaf's values are formed here from
         // that record's input stage (and, for a G, the left partial sums)
@@ -1646,15 +1643,10 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
         const T* pin = nullptr;
         uint32_t pbits = 0;
         if (fz) {
-            const int pisp = ((int)(uint16_t)praw >> 12) & 3;
-            const int posp = ((int)(uint16_t)praw >> 14) & 3;
+            // the parent's stage and partial sums are in LDS as well
             const int px = (int)(uint16_t)(praw >> 16), pz = (int)(uint16_t)(praw >> 48);
-            pin = pisp == SP_LDS
-                      ? (const T*)c.template stage<SP_LDS>(px, k + 1, c.srcA(k + 1, s))
-                      : (const T*)c.template stage<SP_WS>(px, k + 1, c.srcA(k + 1, s));
-            if (fz == 2)
-                pbits = posp == SP_LDS ? *c.template bw<SP_LDS>(pz, k, c.srcB(k, s))
-                                       : *c.template bw<SP_WS>(pz, k, c.srcB(k, s));
+            pin = c.template stage<SP_LDS>(px, k + 1, c.srcA(k + 1, s));
+            if (fz == 2) pbits = *c.template bw<SP_LDS>(pz, k, c.srcB(k, s));
         }
         const M pms = c.pm()[s];
         uint64_t key[8];
@@ -1808,8 +1800,7 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
                 for (int t = 0; t < nflip; ++t)
                     if ((dm >> t) & 1u) word ^= 1u << sj[t];
             }
-            uint32_t* o = osp == SP_LDS ? c.template bw<SP_LDS>(op.y, k, j)
-                                        : c.template bw<SP_WS>(op.y, k, j);
+            uint32_t* o = c.template bw<SP_LDS>(op.y, k, j);
             *o = word;
             c.copy_row(c.rowA(nxt, j), c.rowA(c.cur, src));
             c.copy_row(c.rowB(nxt, j), c.rowB(c.cur, src));
@@ -2157,7 +2148,7 @@ DEV void decode_frame(Ctx<T>& c, const KArgs& a, const uint64_t* __restrict__ sc
                     // a short forking leaf: fused in one wavefront (measured
                     // faster for float32 only, whose workgroups span two
                     // wavefronts; its networks hold at most 32 paths)
-                    if (k <= a.fuse_k) {
+                    if (k <= a.fuse_k && op_isp(op) == SP_LDS && op_osp(op) == SP_LDS) {
                         P = fork_small<T>(c, op, type, k, side, cc, P, praw);
                         q = make_grp(c.tid, c.NT, P);
                         __syncthreads();
@@ -2988,6 +2979,10 @@ std::vector<OpRec> make_records(const pscl_plan* p, const Layout& lay, int k_glo
                 if (kb < 2 || kb > p->fuse_k || (ta != OP_F && ta != OP_G)) continue;
                 if (f_k(a) != kb + 1 || (ia != SP_LDS && ia != SP_WS)) continue;
                 if (((a.meta >> 8) & 15) != 0 || a.y != b.x || f_osp(a) != f_isp(b)) continue;
+                // float32 leaves run fused only with everything in LDS
+                if (p->dtype == PSCL_F32 &&
+                    (ia != SP_LDS || f_isp(b) != SP_LDS || f_osp(b) != SP_LDS))
+                    continue;
                 b.z = (uint16_t)(ta == OP_F ? 1 : 2);
                 a.meta = (uint16_t)((a.meta & ~7u) | OP_NOP);
             }
