@@ -1891,6 +1891,15 @@ DEV int fork_small(Ctx<T>& c, const OpRec& op, int type, int k, int side, int cc
     return prune ? L : C;
 }
 
+// A device-memory pointer read from memory (a job table, a frame record, a
+// plan table) marked as global, so that its loads are global ones rather
+// than generic (flat) ones, whose completion the LDS waits would also cover.
+template <typename T>
+DEV const T* global_row(const void* p) {
+    typedef const __attribute__((address_space(1))) T* GP;
+    return (const T*)(GP)(uintptr_t)p;
+}
+
 // ---------------------------------------------------------------------------
 // Final choice: CRC syndromes, best passing path, u = x G_N, output.
 // ---------------------------------------------------------------------------
@@ -1954,11 +1963,12 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
         }
     }
     __syncthreads();
+    const uint64_t* syn = global_row<uint64_t>(a.syn);
     if (a.has_crc) {
         {
             const uint32_t* x = c.template bw<RSP>(a.root_off, n, si[0]);
             uint64_t acc = 0;
-            for (int w = c.tid; w < W; w += c.NT) acc ^= word_syndrome(x[w], a.syn + (w << 5), nb);
+            for (int w = c.tid; w < W; w += c.NT) acc ^= word_syndrome(x[w], syn + (w << 5), nb);
             xor_steps(64, [&](auto mc) {
                 uint64_t pa, pb;
                 xpair64<decltype(mc)::value>(acc, pa, pb);
@@ -1983,7 +1993,7 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
                 uint64_t acc = 0;
                 for (int t = 0; t < cnt; ++t) {
                     const int w = g + (t << lg);
-                    acc ^= word_syndrome(x[w], a.syn + (w << 5), nb);
+                    acc ^= word_syndrome(x[w], syn + (w << 5), nb);
                 }
                 xor_steps(G, [&](auto mc) {
                     uint64_t pa, pb;
@@ -2053,7 +2063,7 @@ DEV void finish(const Ctx<T>& c, const KArgs& a, int P, int64_t f, uint8_t* u_ha
         const uint32_t* x = c.template bw<RSP>(a.root_off, n, c.sinfo()[0]);
         const int K = a.K;
         for (int t = c.tid; t < K; t += c.NT) {
-            const int p = a.info_pos[t];
+            const int p = global_row<uint16_t>(a.info_pos)[t];
             out_store<SYS>(u_hat + f * K + t, (uint8_t)((x[p >> 5] >> (p & 31)) & 1u));
         }
     }
@@ -2291,7 +2301,7 @@ __global__ void PSCL_KERNEL_BOUNDS(T)
         const KArgs a = D.a;
         const int64_t f = g - J.base;
         bind_plan(c, a, wsb);
-        c.chan = (const T*)J.llr + f * a.N;
+        c.chan = global_row<T>(J.llr) + f * a.N;
         decode_frame<T, WIDE>(c, a, sched + D.op_base, f, J.u_hat, J.crc_ok, J.pm);
     }
 }
@@ -2473,7 +2483,7 @@ __global__ void PSCL_KERNEL_BOUNDS(T)
         const DevPlan& D = plans[d.plan];
         const KArgs a = D.a;
         bind_plan(c, a, wsb);
-        c.chan = (const T*)d.llr;
+        c.chan = global_row<T>(d.llr);
         // outputs written through the L2 at system scope (no write-back of
         // the whole cache per frame), complete before the count
         decode_frame<T, WIDE, true>(c, a, sched + D.op_base, 0, d.u_hat, d.crc_ok, d.pm);
